@@ -1,0 +1,231 @@
+"""Plain FP64 CPU oracle for the exact-exchange operator.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import or call
+this module; it is used by the tests, by the smoke check and by the
+benchmark's CPU-baseline leg.  It shares no code with the HIP library: it
+works from the paper's definitions with NumPy/SciPy primitives, one pair at a
+time, with no packing, pruning, tiling or batching.
+
+What it computes (Ratcliff et al., arXiv:1712.07973, Section 2):
+
+* co-density of a pair, rho_ij(r) = psi_i(r) psi_j(r) for real orbitals
+  (Eq. 8; Eq. 2 defines it with a complex conjugate that is void here);
+* pair potential V_ij, the solution of lap V = -4 pi rho_ij (Eq. 4),
+  obtained by a discrete convolution with a Green's kernel evaluated through
+  FFTs with zero padding for isolated systems (Section 2.1.2);
+* E_x = -1/2 sum_{i,j} f_i f_j  integral rho_ij V_ij  (Eq. 5, one spin channel);
+* the Fock action, (K psi)_i = sum_j f_j V_ij psi_j, which is minus the
+  operator D_X of Eq. 3.
+
+Discrete readings (the paper gives none of these; each is listed in the
+design notes):
+
+* grid point g = (ix, iy, iz) at r = h*g, 0 <= i < n, box L = n h, the
+  integral is h^3 times the grid sum;
+* periodic: FFT grid m = n, kernel 4 pi / |G|^2 with the G = 0 term dropped;
+* free: FFT grid m = 2n with the density in the first octant and zeros
+  elsewhere, the truncated Coulomb kernel 4 pi (1 - cos |G| R) / |G|^2 written
+  as 8 pi sin^2(|G| R / 2) / |G|^2, its G = 0 limit 2 pi R^2 kept, and the
+  potential cropped back to [0, n)^3; R defaults to L (the largest radius
+  that the doubled box keeps free of images);
+* G = 2 pi k / (m h) with k folded to the symmetric range (k > m/2 -> k - m).
+
+Parity pins: see tests/test_oracle_*.py (closed forms for plane waves and
+Gaussians, brute-force sums on tiny grids, invariants, finite differences).
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+import scipy.fft as sfft
+
+PERIODIC = "periodic"
+FREE = "free"
+SCREENED = "screened"  # periodic-style erfc(omega r)/r kernel (screened hybrids)
+
+_WORKERS = int(os.environ.get("EXX_ORACLE_WORKERS", "0")) or (os.cpu_count() or 1)
+
+
+def fft_size(n: int, bc: str) -> int:
+    """FFT grid points per axis: n for periodic, 2n (zero padded) for free."""
+    return 2 * n if bc == FREE else n
+
+
+def default_radius(n: int, h: float) -> float:
+    """Truncation radius of the free-boundary kernel: the box length L = n h."""
+    return n * h
+
+
+def wavevector_sq(m: int, h: float) -> np.ndarray:
+    """|G|^2 on the m^3 FFT grid, array index order [kz][ky][kx]."""
+    k = np.fft.fftfreq(m, d=1.0 / m)  # 0, 1, .., m/2-1, -m/2, .., -1  (integers)
+    g = 2.0 * math.pi * k / (m * h)
+    g2 = g * g
+    return g2[:, None, None] + g2[None, :, None] + g2[None, None, :]
+
+
+def kernel_hat(n: int, h: float, bc: str, R: float | None = None,
+               omega: float = 0.0) -> np.ndarray:
+    """Fourier-space Green's kernel on the FFT grid (real, even in G)."""
+    m = fft_size(n, bc)
+    G2 = wavevector_sq(m, h)
+    out = np.zeros_like(G2)
+    nz = G2 > 0.0
+    if bc == PERIODIC:
+        if omega > 0.0:
+            # Fourier transform of erfc(omega r)/r: 4 pi (1 - exp(-G^2 / 4 omega^2)) / G^2
+            out[nz] = 4.0 * math.pi * (-np.expm1(-G2[nz] / (4.0 * omega * omega))) / G2[nz]
+            out[~nz] = math.pi / (omega * omega)
+        else:
+            out[nz] = 4.0 * math.pi / G2[nz]
+            out[~nz] = 0.0
+    elif bc == FREE:
+        if R is None or R <= 0.0:
+            R = default_radius(n, h)
+        G = np.sqrt(G2[nz])
+        s = np.sin(0.5 * G * R)
+        out[nz] = 8.0 * math.pi * s * s / G2[nz]
+        out[~nz] = 2.0 * math.pi * R * R
+    else:
+        raise ValueError(bc)
+    return out
+
+
+def embed(rho: np.ndarray, m: int) -> np.ndarray:
+    """Place an n^3 array in the first octant of an m^3 zero array."""
+    n = rho.shape[0]
+    if m == n:
+        return rho
+    out = np.zeros((m, m, m), dtype=rho.dtype)
+    out[:n, :n, :n] = rho
+    return out
+
+
+def solve_poisson(rho: np.ndarray, h: float, bc: str, R: float | None = None,
+                  omega: float = 0.0, khat: np.ndarray | None = None) -> np.ndarray:
+    """V with lap V = -4 pi rho (Eq. 4) by FFT convolution with the kernel.
+
+    V = crop( IFFT( K^ . FFT( embed(rho) ) ) ); rho is real so V is real.
+    """
+    n = rho.shape[0]
+    m = fft_size(n, bc)
+    if khat is None:
+        khat = kernel_hat(n, h, bc, R, omega)
+    F = sfft.fftn(embed(rho, m), workers=_WORKERS)
+    V = sfft.ifftn(khat * F, workers=_WORKERS)
+    V = V[:n, :n, :n]
+    return np.ascontiguousarray(V.real)
+
+
+def co_density(psi_i: np.ndarray, psi_j: np.ndarray) -> np.ndarray:
+    """rho_ij = psi_i * psi_j (Eq. 8) for real orbitals."""
+    return psi_i * psi_j
+
+
+def pair_energy(rho: np.ndarray, V: np.ndarray, h: float) -> float:
+    """integral rho V ~ h^3 sum_g rho(g) V(g), summed with math.fsum."""
+    return (h ** 3) * math.fsum((rho * V).ravel().tolist())
+
+
+def exx(psi: np.ndarray, occ: np.ndarray, h: float, bc: str, R: float | None = None,
+        omega: float = 0.0, symmetric: bool = False, want_kpsi: bool = True):
+    """E_x, K psi and the pair-energy matrix e_ij = integral rho_ij V_ij.
+
+    Default: a plain double loop over *ordered* pairs (i, j), one Poisson
+    solve each (so the oracle does not rely on V_ij = V_ji).  With
+    ``symmetric=True`` only i <= j is solved and mirrored, halving the work
+    for large inputs; the symmetry itself is pinned separately.
+    """
+    N = psi.shape[0]
+    khat = kernel_hat(psi.shape[1], h, bc, R, omega)
+    e = np.zeros((N, N))
+    kpsi = np.zeros_like(psi) if want_kpsi else None
+    for i in range(N):
+        for j in range(N):
+            if symmetric and j < i:
+                continue
+            rho = co_density(psi[i], psi[j])
+            V = solve_poisson(rho, h, bc, khat=khat)
+            e[i, j] = pair_energy(rho, V, h)
+            if symmetric:
+                e[j, i] = e[i, j]
+            if want_kpsi:
+                kpsi[i] += occ[j] * V * psi[j]
+                if symmetric and j != i:
+                    kpsi[j] += occ[i] * V * psi[i]
+    E = -0.5 * math.fsum((occ[:, None] * occ[None, :] * e).ravel().tolist())
+    return {"E": E, "kpsi": kpsi, "pair_e": e}
+
+
+def exx_grad_psi(kpsi: np.ndarray, occ: np.ndarray, h: float) -> np.ndarray:
+    """dE_x / dpsi_k(g) = -2 f_k h^3 (K psi)_k(g) for the grid function."""
+    return -2.0 * (h ** 3) * occ[:, None, None, None] * kpsi
+
+
+def exx_grad_occ(pair_e: np.ndarray, occ: np.ndarray) -> np.ndarray:
+    """dE_x / df_k = -sum_j f_j e_kj."""
+    return -(pair_e @ occ)
+
+
+def pair_energies(psi: np.ndarray, pairs, h: float, bc: str, R: float | None = None,
+                  omega: float = 0.0) -> np.ndarray:
+    """e_ij for a list of (i, j) pairs only (sampled checks on large inputs)."""
+    khat = kernel_hat(psi.shape[1], h, bc, R, omega)
+    out = []
+    for i, j in pairs:
+        rho = co_density(psi[i], psi[j])
+        out.append(pair_energy(rho, solve_poisson(rho, h, bc, khat=khat), h))
+    return np.asarray(out)
+
+
+def kpsi_rows(psi: np.ndarray, occ: np.ndarray, rows, h: float, bc: str,
+              R: float | None = None, omega: float = 0.0) -> np.ndarray:
+    """(K psi)_i for the listed orbitals only (N solves per orbital)."""
+    khat = kernel_hat(psi.shape[1], h, bc, R, omega)
+    out = np.zeros((len(rows),) + psi.shape[1:])
+    for r, i in enumerate(rows):
+        for j in range(psi.shape[0]):
+            V = solve_poisson(co_density(psi[i], psi[j]), h, bc, khat=khat)
+            out[r] += occ[j] * V * psi[j]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Tiny-grid brute force: no FFT library at all.
+# ---------------------------------------------------------------------------
+
+def realspace_kernel(n: int, h: float, bc: str, R: float | None = None,
+                     omega: float = 0.0) -> np.ndarray:
+    """K(d) on the m^3 grid of displacements by an explicit inverse DFT sum.
+
+    K(d) = (1/m^3) sum_k K^(k) exp(+2 pi i k.d / m), evaluated with dense
+    exponential matrices (O(m^4)), so that only the kernel formula is shared
+    with the FFT route.
+    """
+    m = fft_size(n, bc)
+    khat = kernel_hat(n, h, bc, R, omega)
+    idx = np.arange(m)
+    E = np.exp(2j * math.pi * np.outer(idx, idx) / m)  # E[d, k]
+    K = np.einsum("ak,bl,cq,klq->abc", E, E, E, khat, optimize=True) / m ** 3
+    return K.real
+
+
+def brute_force_potential(rho: np.ndarray, h: float, bc: str, R: float | None = None,
+                          omega: float = 0.0) -> np.ndarray:
+    """V(g) = sum_{g'} rho(g') K((g - g') mod m), an explicit O(n^3 m^3) sum."""
+    n = rho.shape[0]
+    m = fft_size(n, bc)
+    K = realspace_kernel(n, h, bc, R, omega)
+    V = np.zeros((n, n, n))
+    src = np.argwhere(np.ones((n, n, n), dtype=bool))
+    for (a, b, c) in src:
+        w = rho[a, b, c]
+        if w == 0.0:
+            continue
+        za = (np.arange(n) - a) % m
+        yb = (np.arange(n) - b) % m
+        xc = (np.arange(n) - c) % m
+        V += w * K[np.ix_(za, yb, xc)]
+    return V
