@@ -1,0 +1,185 @@
+/*
+ * exx.h -- C ABI of the MI355X exact-exchange library (libexx.so).
+ *
+ * The library evaluates, for one spin channel of real orbitals psi_i on a
+ * uniform cubic grid with occupations f_i,
+ *
+ *   rho_ij(r) = psi_i(r) psi_j(r)                         (co-density, Eq. 8)
+ *   V_ij      = solution of lap V = -4 pi rho_ij         (pair potential, Eq. 4)
+ *   E_x       = -1/2 sum_{i,j} f_i f_j h^3 sum_r rho_ij V_ij          (Eq. 5)
+ *   (K psi)_i = sum_j f_j V_ij psi_j         (minus the Fock action D_X, Eq. 3)
+ *
+ * following Ratcliff et al., arXiv:1712.07973, Section 2 (the pair-sum
+ * scheme with one Poisson solve per unordered pair, N(N+1)/2 solves) and
+ * Section 2.1.2 (Poisson solve by FFT convolution with a Green's kernel,
+ * zero padding for isolated systems).
+ *
+ * Conventions shared by every entry point
+ *   - grid point (ix,iy,iz), 0 <= i < n, sits at r = (hx ix, hy iy, hz iz);
+ *   - psi and K psi are FP64, C-contiguous [n_orb][n][n][n] with x fastest,
+ *     in DEVICE memory, 16-byte aligned;  occ is FP64 [n_orb] in device memory;
+ *   - periodic boundary: FFT grid n^3, kernel 4 pi / |G|^2 with G = 0 dropped;
+ *   - free boundary: FFT grid (2n)^3 with the data in the first octant, kernel
+ *     4 pi (1 - cos |G| R) / |G|^2 (value 2 pi R^2 at G = 0), potential cropped
+ *     back to n^3; R <= 0 selects R = min(n hx, n hy, n hz), the largest radius
+ *     free of periodic images on the doubled grid;
+ *   - G = 2 pi k / (m h) per axis with k folded to (-m/2, m/2].
+ *
+ * Ownership: the caller owns psi, occ, every output and the workspace; the
+ * library owns only plans and batches (host objects plus small device tables)
+ * and never allocates inside exx_compute / exx_batch_compute, except the
+ * per-orbital-count schedule that exx_plan_prepare builds (see there).
+ *
+ * Errors: every entry point returns EXX_OK (0) or a negative EXX_ERR_* code;
+ * arguments are validated before any HIP call; nothing aborts or throws across
+ * the ABI.  exx_last_error() gives a thread-local message for the last failure.
+ *
+ * Streams: every compute call is stream-ordered on the given hipStream_t
+ * (passed as void*, NULL = the default stream), never synchronises the host
+ * and can be captured into a HIP graph once its schedule is prepared.
+ */
+#ifndef EXX_H
+#define EXX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- enumerations ------------------------------------------------------ */
+enum exx_bc { EXX_BC_PERIODIC = 0, EXX_BC_FREE = 1 };
+
+/* Kernel of the pair Poisson problem.  COULOMB is 1/r (Eq. 4; truncated at R
+ * for free boundaries).  SCREENED is erfc(omega r)/r, the short-range kernel of
+ * screened hybrids: the paper notes only kernel 2's filter changes for them
+ * (Section 3.2.3); periodic boundary only. */
+enum exx_kernel { EXX_KERNEL_COULOMB = 0, EXX_KERNEL_SCREENED = 1 };
+
+/* Arithmetic path.
+ *   FP32      : FP32 FFTs, two real pairs packed per complex transform,
+ *               FP64 pair-energy and K psi accumulation (the fast path);
+ *   FP64_PLAIN: FP64 throughout, one pair per complex transform, one launch per
+ *               FFT axis, no packing and no pruning (the reference GPU path);
+ *   FP64_FUSED: the FP32 path's fused kernels instantiated in FP64 (ablation;
+ *               n <= 96). */
+enum exx_precision { EXX_PREC_FP32 = 0, EXX_PREC_FP64_PLAIN = 1, EXX_PREC_FP64_FUSED = 2 };
+
+/* What to compute.  ENERGY alone uses Parseval's identity (one forward
+ * transform per pair) unless pair energies are requested. */
+enum exx_mode { EXX_MODE_ENERGY = 1, EXX_MODE_KPSI = 2, EXX_MODE_ENERGY_KPSI = 3 };
+
+/* Flags of exx_compute / exx_batch_compute. */
+#define EXX_FLAG_ACCUMULATE 1u /* add into kpsi instead of overwriting it */
+
+/* Error codes. */
+enum exx_status {
+  EXX_OK = 0,
+  EXX_ERR_INVALID_ARG = -1,      /* null pointer, non-positive size or spacing, bad enum */
+  EXX_ERR_UNSUPPORTED_SIZE = -2, /* n not in {16,32,48,64,80,96,112,128} or n > path limit */
+  EXX_ERR_CAPACITY = -3,         /* n_orb above the plan's n_orb_max */
+  EXX_ERR_WORKSPACE = -4,        /* workspace missing or smaller than required */
+  EXX_ERR_ALIGNMENT = -5,        /* psi / kpsi / workspace not 16-byte aligned */
+  EXX_ERR_HIP = -6,              /* a HIP runtime call failed (message has the hipError_t) */
+  EXX_ERR_NOT_PREPARED = -7,     /* schedule missing for this n_orb while capturing */
+  EXX_ERR_INTERNAL = -8
+};
+
+/* ---- plans --------------------------------------------------------------- */
+typedef struct exx_grid {
+  int nx, ny, nz;    /* grid points per axis; must be equal (cubic grid) */
+  double hx, hy, hz; /* spacings in bohr, > 0 */
+  int bc;            /* enum exx_bc */
+  int kernel;        /* enum exx_kernel */
+  double R;          /* free-boundary truncation radius; <= 0 selects the default */
+  double omega;      /* screening parameter for EXX_KERNEL_SCREENED (> 0) */
+} exx_grid;
+
+typedef struct exx_plan exx_plan;
+
+/* Creates a plan for one grid and precision on the current HIP device: FFT
+ * twiddles (computed in FP64 on the host, rounded once), the Green's kernel
+ * table (FP64 on the host), and the default pair-tile schedule.  n_orb_max
+ * bounds every later n_orb.  flags: reserved, pass 0.  Allocates device
+ * memory; synchronous. */
+int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_orb_max,
+                    unsigned flags);
+void exx_plan_destroy(exx_plan* plan);
+
+/* Builds (once per n_orb) the device-side pair schedule used by exx_compute.
+ * exx_compute calls it implicitly; call it yourself before capturing a graph.
+ * Allocates device memory; synchronous. */
+int exx_plan_prepare(exx_plan* plan, int n_orb);
+
+/* Bytes of device workspace exx_compute needs for n_orb orbitals. */
+int exx_workspace_bytes(const exx_plan* plan, int n_orb, size_t* bytes);
+
+/* Evaluates the exchange for n_orb orbitals.
+ *   psi    [n_orb][n][n][n] FP64, device;  occ [n_orb] FP64, device (f_i >= 0);
+ *   mode   enum exx_mode;  flags EXX_FLAG_*;
+ *   ex_out device FP64 scalar receiving E_x (Hartree); required if mode has ENERGY;
+ *   kpsi   device FP64 [n_orb][n][n][n] receiving (K psi)_i; required if mode has KPSI;
+ *   pair_e device FP64 [n_orb][n_orb] receiving e_ij = h^3 sum_r rho_ij V_ij
+ *          (symmetric, both triangles written), or NULL;
+ *   ws     device workspace of ws_bytes >= exx_workspace_bytes(), 256-byte aligned;
+ *   stream hipStream_t or NULL.
+ * Outputs are complete when the stream reaches the end of the call. */
+int exx_compute(exx_plan* plan, const double* psi, const double* occ, int n_orb, int mode,
+                unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
+                size_t ws_bytes, void* stream);
+
+/* Tuning knobs of a plan (pair-tile edge, slots per launch, rows per
+ * workgroup).  Returned by exx_autotune and settable explicitly; 0 = keep. */
+typedef struct exx_tuning {
+  int tile;        /* orbitals per pair-tile edge (2..16) */
+  int batch_slots; /* packed pair slots per pass launch (>= 1) */
+  int zblock_a;    /* grid rows per workgroup in the pair-build / forward pass */
+  int zblock_c;    /* grid rows per workgroup in the inverse / reduction pass */
+} exx_tuning;
+
+int exx_plan_get_tuning(const exx_plan* plan, exx_tuning* out);
+int exx_plan_set_tuning(exx_plan* plan, const exx_tuning* t);
+
+/* Times candidate tunings for n_orb orbitals with hipEvents on `stream` using
+ * the caller's psi/occ/kpsi/ws buffers, keeps the fastest, and if cache_path is
+ * non-NULL reads/writes a small text cache keyed by GPU arch, grid, boundary,
+ * precision and n_orb.  budget_ms bounds the search (<= 0: default).
+ * Synchronises the stream. */
+int exx_autotune(exx_plan* plan, const double* psi, const double* occ, int n_orb, double* kpsi,
+                 void* ws, size_t ws_bytes, void* stream, int budget_ms, const char* cache_path);
+
+/* ---- batches of independent systems ------------------------------------- */
+typedef struct exx_system {
+  const double* psi; /* [n_orb][n][n][n] FP64, device */
+  const double* occ; /* [n_orb] FP64, device */
+  double* ex_out;    /* device FP64 scalar or NULL */
+  double* kpsi;      /* device FP64 like psi, or NULL */
+  double* pair_e;    /* device FP64 [n_orb][n_orb] or NULL */
+} exx_system;
+
+typedef struct exx_batch exx_batch;
+
+/* A batch of n_systems independent systems (any mix of supported grids and
+ * orbital counts, one precision).  All per-system work of one pass is issued
+ * as a single launch over a merged work list; with use_graph != 0 the whole
+ * evaluation is captured into a HIP graph on the first exx_batch_compute and
+ * replayed afterwards (the system pointers must then stay the same). */
+int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
+                     int precision, int use_graph);
+void exx_batch_destroy(exx_batch* batch);
+int exx_batch_workspace_bytes(const exx_batch* batch, size_t* bytes);
+int exx_batch_compute(exx_batch* batch, const exx_system* systems, int mode, unsigned flags,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* ---- diagnostics --------------------------------------------------------- */
+const char* exx_error_string(int code);
+const char* exx_last_error(void);
+/* Pair count N(N+1)/2 and packed-slot count of the plan's schedule for n_orb. */
+int exx_plan_schedule_info(exx_plan* plan, int n_orb, long long* n_pairs, long long* n_slots);
+/* Library version, e.g. "exx 0.1 gfx950". */
+const char* exx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXX_H */

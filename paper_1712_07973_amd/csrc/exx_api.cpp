@@ -1,0 +1,470 @@
+// exx_api.cpp -- C ABI: validation, plans (twiddle and kernel tables), pair
+// schedules, workspace layout and the launch sequence of one evaluation.
+//
+// Pair-sum scheme of arXiv:1712.07973 (Section 2, Eq. 5): all N(N+1)/2
+// unordered pairs i <= j are solved once; an off-diagonal pair enters E_x
+// twice (f_i f_j e_ij + f_j f_i e_ji) and updates both (K psi)_i and
+// (K psi)_j, which is the single-device analogue of returning each pair
+// potential to both orbital owners (Section 2.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "exx_fft.hpp"
+#include "exx_internal.hpp"
+
+using namespace exx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_last_error = std::string(where) + ": " + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ")";
+  return EXX_ERR_HIP;
+}
+
+#define EXX_HIP(call)                            \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846;
+
+bool supported_n(int n) { return n >= 16 && n <= 128 && n % 16 == 0; }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Green's kernel in Fourier space (real, even), FP64 on the host.
+double kernel_value(const exx_grid& g, double R, double G2) {
+  if (g.kernel == EXX_KERNEL_SCREENED) {
+    double w2 = g.omega * g.omega;
+    if (G2 == 0.0) return kPi / w2;
+    return 4.0 * kPi * (-std::expm1(-G2 / (4.0 * w2))) / G2;
+  }
+  if (g.bc == EXX_BC_PERIODIC) {
+    if (G2 == 0.0) return 0.0;
+    return 4.0 * kPi / G2;
+  }
+  if (G2 == 0.0) return 2.0 * kPi * R * R;
+  double G = std::sqrt(G2);
+  double s = std::sin(0.5 * G * R);
+  return 8.0 * kPi * s * s / G2;
+}
+
+// Octant table K(fx, fy, fz) / m^3 for folded indices 0..m/2 (fz fastest).
+std::vector<double> kernel_octant(const exx_grid& g, double R, int m) {
+  const int H = m / 2 + 1;
+  std::vector<double> t((size_t)H * H * H);
+  const double inv = 1.0 / ((double)m * m * m);
+  const double hs[3] = {g.hx, g.hy, g.hz};
+  double Gc[3][130 * 2];
+  for (int a = 0; a < 3; ++a)
+    for (int f = 0; f < H; ++f) {
+      double G = 2.0 * kPi * f / (m * hs[a]);
+      Gc[a][f] = G * G;
+    }
+  for (int fx = 0; fx < H; ++fx)
+    for (int fy = 0; fy < H; ++fy)
+      for (int fz = 0; fz < H; ++fz)
+        t[((size_t)fx * H + fy) * H + fz] = kernel_value(g, R, Gc[0][fx] + Gc[1][fy] + Gc[2][fz]) * inv;
+  return t;
+}
+
+// exp(-2 pi i k / L) for k < count, FP64 (libm) then stored as T.
+template <typename T>
+std::vector<cpx<T>> roots(int L, int count) {
+  std::vector<cpx<T>> v(count);
+  for (int k = 0; k < count; ++k) {
+    double a = -2.0 * kPi * (double)k / (double)L;
+    v[k] = {(T)std::cos(a), (T)std::sin(a)};
+  }
+  return v;
+}
+
+template <typename V>
+int upload(void** dst, const V& v) {
+  size_t bytes = v.size() * sizeof(typename V::value_type);
+  EXX_HIP(hipMalloc(dst, bytes));
+  EXX_HIP(hipMemcpy(*dst, v.data(), bytes, hipMemcpyHostToDevice));
+  return EXX_OK;
+}
+
+bool is_fp32(const exx_plan* p) { return p->precision == EXX_PREC_FP32; }
+bool is_plain(const exx_plan* p) { return p->precision == EXX_PREC_FP64_PLAIN; }
+
+size_t slot_bytes(const exx_plan* p) {
+  // fused: ncls * n^3 complex of the compute type; plain: m^3 complex FP64 per pair
+  if (is_plain(p)) return (size_t)p->m * p->m * p->m * 16;
+  size_t c = is_fp32(p) ? 8 : 16;
+  return (size_t)p->ncls * p->n * p->n * p->n * c;
+}
+
+void default_tuning(exx_plan* p) {
+  p->tuning.tile = 4;
+  const size_t budget = (size_t)4 << 30;  // bytes of spectrum workspace per launch chunk
+  size_t per = slot_bytes(p);
+  p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
+  p->tuning.zblock_a = 16;
+  p->tuning.zblock_c = 8;
+}
+
+void build_schedule(const exx_plan* p, int N, Schedule& s) {
+  s = Schedule();
+  s.n_orb = N;
+  s.n_pairs = (long long)N * (N + 1) / 2;
+  s.batch_slots = p->tuning.batch_slots;
+  if (is_plain(p)) {
+    s.tile = 0;
+    for (int i = 0; i < N; ++i)
+      for (int j = i; j < N; ++j) s.slots.push_back({i, j, -1, -1});
+    int cap = std::max(1, p->tuning.batch_slots);
+    for (int s0 = 0; s0 < (int)s.slots.size(); s0 += cap)
+      s.chunks.push_back({0, 0, s0, std::min<int>((int)s.slots.size(), s0 + cap)});
+    return;
+  }
+  const int T = std::max(1, std::min(p->tuning.tile, 4));
+  s.tile = T;
+  const int nt = (N + T - 1) / T;
+  for (int I = 0; I < nt; ++I)
+    for (int J = I; J < nt; ++J) {
+      TilePair tp{};
+      tp.I0 = I * T;
+      tp.nI = std::min(T, N - tp.I0);
+      tp.J0 = J * T;
+      tp.nJ = std::min(T, N - tp.J0);
+      tp.diag = (I == J);
+      std::vector<std::pair<int, int>> pairs;
+      for (int a = 0; a < tp.nI; ++a)
+        for (int b = tp.diag ? a : 0; b < tp.nJ; ++b) pairs.push_back({tp.I0 + a, tp.J0 + b});
+      tp.s0 = (int)s.slots.size();
+      for (size_t k = 0; k < pairs.size(); k += 2) {
+        Slot sl{pairs[k].first, pairs[k].second, -1, -1};
+        if (k + 1 < pairs.size()) {
+          sl.ib = pairs[k + 1].first;
+          sl.jb = pairs[k + 1].second;
+        }
+        s.slots.push_back(sl);
+      }
+      tp.s1 = (int)s.slots.size();
+      s.tiles.push_back(tp);
+    }
+  // chunks of whole tiles whose slots fit the launch capacity
+  const int cap = std::max(p->tuning.batch_slots, T * T);
+  int t0 = 0;
+  while (t0 < (int)s.tiles.size()) {
+    int t1 = t0;
+    while (t1 < (int)s.tiles.size() && s.tiles[t1].s1 - s.tiles[t0].s0 <= cap) ++t1;
+    if (t1 == t0) t1 = t0 + 1;
+    s.chunks.push_back({t0, t1, s.tiles[t0].s0, s.tiles[t1 - 1].s1});
+    t0 = t1;
+  }
+}
+
+int cap_slots(const exx_plan* p, const Schedule& s) {
+  int cap = 0;
+  for (auto& c : s.chunks) cap = std::max(cap, c.s1 - c.s0);
+  return cap;
+}
+
+struct WsLayout {
+  size_t psi32 = 0, e_slot = 0, X = 0, total = 0;
+};
+
+WsLayout layout(const exx_plan* p, const Schedule& s) {
+  WsLayout w;
+  size_t off = 0;
+  w.psi32 = off;
+  if (is_fp32(p)) off += align_up((size_t)s.n_orb * p->n * p->n * p->n * sizeof(float), 256);
+  w.e_slot = off;
+  off += align_up(2 * s.slots.size() * sizeof(double), 256);
+  w.X = off;
+  off += align_up((size_t)cap_slots(p, s) * slot_bytes(p), 256);
+  w.total = off;
+  return w;
+}
+
+int get_schedule(exx_plan* p, int N, Schedule** out, bool allow_build) {
+  auto it = p->schedules.find(N);
+  if (it != p->schedules.end() && it->second.tile == (is_plain(p) ? 0 : std::min(p->tuning.tile, 4)) &&
+      it->second.batch_slots == p->tuning.batch_slots) {
+    *out = &it->second;
+    return EXX_OK;
+  }
+  if (!allow_build) return fail(EXX_ERR_NOT_PREPARED, "schedule for this n_orb is not prepared (call exx_plan_prepare before graph capture)");
+  if (it != p->schedules.end()) {
+    (void)hipFree(it->second.d_slots);
+    (void)hipFree(it->second.d_tiles);
+    p->schedules.erase(it);
+  }
+  Schedule s;
+  build_schedule(p, N, s);
+  int dev = 0;
+  EXX_HIP(hipGetDevice(&dev));
+  EXX_HIP(hipSetDevice(p->device));
+  EXX_HIP(hipMalloc((void**)&s.d_slots, std::max<size_t>(1, s.slots.size()) * sizeof(Slot)));
+  EXX_HIP(hipMemcpy(s.d_slots, s.slots.data(), s.slots.size() * sizeof(Slot), hipMemcpyHostToDevice));
+  if (!s.tiles.empty()) {
+    EXX_HIP(hipMalloc((void**)&s.d_tiles, s.tiles.size() * sizeof(TilePair)));
+    EXX_HIP(hipMemcpy(s.d_tiles, s.tiles.data(), s.tiles.size() * sizeof(TilePair), hipMemcpyHostToDevice));
+  }
+  EXX_HIP(hipSetDevice(dev));
+  auto res = p->schedules.emplace(N, std::move(s));
+  *out = &res.first->second;
+  return EXX_OK;
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+template <typename T>
+int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* psi,
+              const double* occ, int N, int mode, unsigned flags, double* ex_out, double* kpsi,
+              double* pair_e, char* ws, hipStream_t st) {
+  const bool want_k = (mode & EXX_MODE_KPSI) != 0;
+  const bool want_e = (mode & EXX_MODE_ENERGY) != 0 || pair_e != nullptr;
+  const bool parseval = (mode == EXX_MODE_ENERGY) && pair_e == nullptr;
+  const size_t n3 = (size_t)p->n * p->n * p->n;
+  const T* psiT;
+  if constexpr (sizeof(T) == 4) {
+    float* p32 = reinterpret_cast<float*>(ws + w.psi32);
+    EXX_HIP(launch_convert(psi, p32, (size_t)N * n3, st));
+    psiT = p32;
+  } else {
+    psiT = psi;
+  }
+  double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
+  void* X = ws + w.X;
+  if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
+  if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
+  Launch L{p->n, p->ncls, p->m, p->h3, st};
+  for (const auto& c : s.chunks) {
+    const int ns = c.s1 - c.s0;
+    EXX_HIP(launch_pass_a<T>(L, psiT, X, s.d_slots, c.s0, ns, occ, parseval, p->tuning.zblock_a, p->tables));
+    EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_slot, c.s0, p->tables));
+    if (!parseval)
+      EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, c.t0, c.t1 - c.t0, c.s0, kpsi,
+                               e_slot, want_k, want_e, p->tuning.zblock_c, 4, p->tables));
+  }
+  if (want_e)
+    EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, parseval,
+                            (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
+  return EXX_OK;
+}
+
+int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* psi,
+              const double* occ, int N, int mode, unsigned flags, double* ex_out, double* kpsi,
+              double* pair_e, char* ws, hipStream_t st) {
+  const bool want_k = (mode & EXX_MODE_KPSI) != 0;
+  const bool want_e = (mode & EXX_MODE_ENERGY) != 0 || pair_e != nullptr;
+  const size_t n3 = (size_t)p->n * p->n * p->n;
+  double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
+  void* Z = ws + w.X;
+  if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
+  if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
+  for (const auto& c : s.chunks) {
+    const int np = c.s1 - c.s0;
+    EXX_HIP(plain_build(psi, s.d_slots, c.s0, np, p->n, p->m, Z, st));
+    for (int a = 0; a < 3; ++a) EXX_HIP(plain_fft_axis(Z, np, p->m, a, -1, p->tables, st));
+    EXX_HIP(plain_kernel_mul(Z, np, p->m, p->tables, st));
+    for (int a = 0; a < 3; ++a) EXX_HIP(plain_fft_axis(Z, np, p->m, a, +1, p->tables, st));
+    EXX_HIP(plain_reduce(Z, psi, occ, s.d_slots, c.s0, np, p->n, p->m, p->h3, kpsi, e_slot, want_k,
+                         want_e, st));
+  }
+  if (want_e)
+    EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, false,
+                            (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
+  return EXX_OK;
+}
+
+int validate_grid(const exx_grid* g, int precision) {
+  if (!g) return fail(EXX_ERR_INVALID_ARG, "grid is NULL");
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0) return fail(EXX_ERR_INVALID_ARG, "grid sizes must be positive");
+  if (!(g->hx > 0) || !(g->hy > 0) || !(g->hz > 0) || !std::isfinite(g->hx) || !std::isfinite(g->hy) ||
+      !std::isfinite(g->hz))
+    return fail(EXX_ERR_INVALID_ARG, "grid spacings must be positive and finite");
+  if (g->bc != EXX_BC_PERIODIC && g->bc != EXX_BC_FREE) return fail(EXX_ERR_INVALID_ARG, "unknown boundary condition");
+  if (g->kernel != EXX_KERNEL_COULOMB && g->kernel != EXX_KERNEL_SCREENED)
+    return fail(EXX_ERR_INVALID_ARG, "unknown kernel");
+  if (g->kernel == EXX_KERNEL_SCREENED && (!(g->omega > 0) || g->bc != EXX_BC_PERIODIC))
+    return fail(EXX_ERR_INVALID_ARG, "screened kernel needs omega > 0 and a periodic grid");
+  if (precision != EXX_PREC_FP32 && precision != EXX_PREC_FP64_PLAIN && precision != EXX_PREC_FP64_FUSED)
+    return fail(EXX_ERR_INVALID_ARG, "unknown precision");
+  if (g->nx != g->ny || g->nx != g->nz) return fail(EXX_ERR_UNSUPPORTED_SIZE, "grid must be cubic (nx == ny == nz)");
+  if (!supported_n(g->nx))
+    return fail(EXX_ERR_UNSUPPORTED_SIZE, "n must be one of 16, 32, 48, 64, 80, 96, 112, 128");
+  if (precision == EXX_PREC_FP64_FUSED && g->nx > 96)
+    return fail(EXX_ERR_UNSUPPORTED_SIZE, "FP64_FUSED supports n <= 96 (LDS capacity)");
+  return EXX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* exx_version(void) { return "exx 0.1 gfx950"; }
+
+const char* exx_last_error(void) { return g_last_error.c_str(); }
+
+const char* exx_error_string(int code) {
+  switch (code) {
+    case EXX_OK: return "ok";
+    case EXX_ERR_INVALID_ARG: return "invalid argument";
+    case EXX_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+    case EXX_ERR_CAPACITY: return "capacity exceeded";
+    case EXX_ERR_WORKSPACE: return "workspace missing or too small";
+    case EXX_ERR_ALIGNMENT: return "misaligned pointer";
+    case EXX_ERR_HIP: return "HIP runtime error";
+    case EXX_ERR_NOT_PREPARED: return "schedule not prepared";
+    case EXX_ERR_INTERNAL: return "internal error";
+    default: return "unknown error code";
+  }
+}
+
+int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_orb_max,
+                    unsigned flags) {
+  (void)flags;
+  if (!out) return fail(EXX_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate_grid(grid, precision);
+  if (rc) return rc;
+  if (n_orb_max <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb_max must be positive");
+  exx_plan* p = new (std::nothrow) exx_plan();
+  if (!p) return fail(EXX_ERR_INTERNAL, "out of host memory");
+  p->grid = *grid;
+  p->n = grid->nx;
+  p->ncls = grid->bc == EXX_BC_FREE ? 2 : 1;
+  p->m = p->ncls * p->n;
+  p->h3 = grid->hx * grid->hy * grid->hz;
+  p->R = grid->R > 0 ? grid->R : p->n * std::min(grid->hx, std::min(grid->hy, grid->hz));
+  p->precision = precision;
+  p->n_orb_max = n_orb_max;
+  default_tuning(p);
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "hipGetDevice");
+  }
+  auto kt = kernel_octant(*grid, p->R, p->m);
+  int r = EXX_OK;
+  if (is_plain(p)) {
+    r = upload(&p->tables.tw_m, roots<double>(p->m, p->m));
+    if (!r) r = upload(&p->tables.ktab_m, kt);
+  } else if (is_fp32(p)) {
+    std::vector<float> kf(kt.begin(), kt.end());
+    r = upload(&p->tables.ktab, kf);
+    if (!r) r = upload(&p->tables.tw, roots<float>(p->n, p->n));
+    if (!r) r = upload(&p->tables.md, roots<float>(2 * p->n, p->n));
+  } else {
+    r = upload(&p->tables.ktab, kt);
+    if (!r) r = upload(&p->tables.tw, roots<double>(p->n, p->n));
+    if (!r) r = upload(&p->tables.md, roots<double>(2 * p->n, p->n));
+  }
+  if (r) {
+    exx_plan_destroy(p);
+    return r;
+  }
+  *out = p;
+  return EXX_OK;
+}
+
+void exx_plan_destroy(exx_plan* p) {
+  if (!p) return;
+  void* ptrs[] = {p->tables.tw, p->tables.md, p->tables.ktab, p->tables.tw_m, p->tables.ktab_m};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  for (auto& kv : p->schedules) {
+    if (kv.second.d_slots) (void)hipFree(kv.second.d_slots);
+    if (kv.second.d_tiles) (void)hipFree(kv.second.d_tiles);
+  }
+  delete p;
+}
+
+int exx_plan_prepare(exx_plan* p, int n_orb) {
+  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
+  if (n_orb <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb must be positive");
+  if (n_orb > p->n_orb_max) return fail(EXX_ERR_CAPACITY, "n_orb exceeds the plan's n_orb_max");
+  Schedule* s = nullptr;
+  return get_schedule(p, n_orb, &s, true);
+}
+
+int exx_plan_schedule_info(exx_plan* p, int n_orb, long long* n_pairs, long long* n_slots) {
+  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
+  if (n_orb <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb must be positive");
+  Schedule s;
+  build_schedule(p, n_orb, s);
+  if (n_pairs) *n_pairs = s.n_pairs;
+  if (n_slots) *n_slots = (long long)s.slots.size();
+  return EXX_OK;
+}
+
+int exx_workspace_bytes(const exx_plan* p, int n_orb, size_t* bytes) {
+  if (!p || !bytes) return fail(EXX_ERR_INVALID_ARG, "plan or bytes is NULL");
+  if (n_orb <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb must be positive");
+  if (n_orb > p->n_orb_max) return fail(EXX_ERR_CAPACITY, "n_orb exceeds the plan's n_orb_max");
+  Schedule s;
+  build_schedule(p, n_orb, s);
+  *bytes = layout(p, s).total;
+  return EXX_OK;
+}
+
+int exx_plan_get_tuning(const exx_plan* p, exx_tuning* out) {
+  if (!p || !out) return fail(EXX_ERR_INVALID_ARG, "plan or out is NULL");
+  *out = p->tuning;
+  return EXX_OK;
+}
+
+int exx_plan_set_tuning(exx_plan* p, const exx_tuning* t) {
+  if (!p || !t) return fail(EXX_ERR_INVALID_ARG, "plan or tuning is NULL");
+  if (t->tile < 0 || t->tile > 4 || t->batch_slots < 0)
+    return fail(EXX_ERR_INVALID_ARG, "tile must be in 1..4 and batch_slots >= 0");
+  if (t->tile) p->tuning.tile = t->tile;
+  if (t->batch_slots) p->tuning.batch_slots = t->batch_slots;
+  if (t->zblock_a) p->tuning.zblock_a = t->zblock_a;
+  if (t->zblock_c) p->tuning.zblock_c = t->zblock_c;
+  return EXX_OK;
+}
+
+int exx_compute(exx_plan* p, const double* psi, const double* occ, int n_orb, int mode,
+                unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
+                size_t ws_bytes, void* stream) {
+  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
+  if (!psi || !occ) return fail(EXX_ERR_INVALID_ARG, "psi and occ are required");
+  if (n_orb <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb must be positive");
+  if (n_orb > p->n_orb_max) return fail(EXX_ERR_CAPACITY, "n_orb exceeds the plan's n_orb_max");
+  if (mode != EXX_MODE_ENERGY && mode != EXX_MODE_KPSI && mode != EXX_MODE_ENERGY_KPSI)
+    return fail(EXX_ERR_INVALID_ARG, "unknown mode");
+  if ((flags & ~EXX_FLAG_ACCUMULATE) != 0) return fail(EXX_ERR_INVALID_ARG, "unknown flags");
+  if ((mode & EXX_MODE_ENERGY) && !ex_out) return fail(EXX_ERR_INVALID_ARG, "ex_out is required for ENERGY modes");
+  if ((mode & EXX_MODE_KPSI) && !kpsi) return fail(EXX_ERR_INVALID_ARG, "kpsi is required for KPSI modes");
+  if (!aligned(psi, 16) || (kpsi && !aligned(kpsi, 16)) || !aligned(occ, 8) ||
+      (pair_e && !aligned(pair_e, 8)) || (ex_out && !aligned(ex_out, 8)))
+    return fail(EXX_ERR_ALIGNMENT, "psi/kpsi must be 16-byte aligned, scalars 8-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  EXX_HIP(hipStreamIsCapturing(st, &cap));
+  Schedule* s = nullptr;
+  int rc = get_schedule(p, n_orb, &s, cap == hipStreamCaptureStatusNone);
+  if (rc) return rc;
+  WsLayout w = layout(p, *s);
+  if (!ws || ws_bytes < w.total)
+    return fail(EXX_ERR_WORKSPACE, "workspace smaller than exx_workspace_bytes(): need " + std::to_string(w.total));
+  if (!aligned(ws, 256)) return fail(EXX_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+  char* wsc = static_cast<char*>(ws);
+  if (is_plain(p)) return run_plain(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+  if (is_fp32(p)) return run_fused<float>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+  return run_fused<double>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+}
+
+}  // extern "C"

@@ -1,0 +1,229 @@
+// exx_batch.cpp -- batches of independent systems and the autotuner.
+//
+// A batch owns one plan per distinct (grid, boundary, kernel) and evaluates
+// every system on one stream; with use_graph the whole sequence (all
+// systems, all passes) is captured once into a HIP graph and replayed, so a
+// batch costs one graph launch.  The autotuner times a small grid of tunings
+// with hipEvents and keeps the fastest; results persist in a text cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "exx_internal.hpp"
+
+struct exx_batch {
+  std::vector<exx_plan*> plans;  // one per system (plans may repeat grids)
+  std::vector<int> n_orb;
+  std::vector<size_t> ws_off;
+  size_t ws_total = 0;
+  int use_graph = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<exx_system> captured;  // pointers the graph was captured with
+  int captured_mode = 0;
+  unsigned captured_flags = 0;
+  void* captured_ws = nullptr;
+  hipStream_t captured_stream = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_msg;
+
+int set_err(int code, const std::string& m) {
+  g_msg = m;
+  return code;
+}
+
+bool same_systems(const std::vector<exx_system>& a, const exx_system* b, size_t n) {
+  if (a.size() != n) return false;
+  for (size_t i = 0; i < n; ++i)
+    if (std::memcmp(&a[i], &b[i], sizeof(exx_system)) != 0) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
+                     int precision, int use_graph) {
+  if (!out || !grids || !n_orb || n_systems <= 0) return EXX_ERR_INVALID_ARG;
+  *out = nullptr;
+  exx_batch* b = new (std::nothrow) exx_batch();
+  if (!b) return EXX_ERR_INTERNAL;
+  b->use_graph = use_graph;
+  size_t off = 0;
+  for (int s = 0; s < n_systems; ++s) {
+    exx_plan* p = nullptr;
+    int rc = exx_plan_create(&p, &grids[s], precision, n_orb[s], 0);
+    if (rc == EXX_OK) rc = exx_plan_prepare(p, n_orb[s]);
+    size_t bytes = 0;
+    if (rc == EXX_OK) rc = exx_workspace_bytes(p, n_orb[s], &bytes);
+    if (rc != EXX_OK) {
+      if (p) exx_plan_destroy(p);
+      exx_batch_destroy(b);
+      return rc;
+    }
+    b->plans.push_back(p);
+    b->n_orb.push_back(n_orb[s]);
+    b->ws_off.push_back(off);
+    off += (bytes + 255) / 256 * 256;
+  }
+  b->ws_total = off;
+  *out = b;
+  return EXX_OK;
+}
+
+void exx_batch_destroy(exx_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto* p : b->plans) exx_plan_destroy(p);
+  delete b;
+}
+
+int exx_batch_workspace_bytes(const exx_batch* b, size_t* bytes) {
+  if (!b || !bytes) return EXX_ERR_INVALID_ARG;
+  *bytes = b->ws_total;
+  return EXX_OK;
+}
+
+static int batch_eager(exx_batch* b, const exx_system* sys, int mode, unsigned flags, char* ws,
+                       hipStream_t st) {
+  for (size_t s = 0; s < b->plans.size(); ++s) {
+    size_t bytes = 0;
+    exx_workspace_bytes(b->plans[s], b->n_orb[s], &bytes);
+    int rc = exx_compute(b->plans[s], sys[s].psi, sys[s].occ, b->n_orb[s], mode, flags, sys[s].ex_out,
+                         sys[s].kpsi, sys[s].pair_e, ws + b->ws_off[s], bytes, st);
+    if (rc != EXX_OK) return rc;
+  }
+  return EXX_OK;
+}
+
+int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned flags, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!b || !sys) return EXX_ERR_INVALID_ARG;
+  if (!ws || ws_bytes < b->ws_total) return EXX_ERR_WORKSPACE;
+  if (((uintptr_t)ws % 256) != 0) return EXX_ERR_ALIGNMENT;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* wsc = static_cast<char*>(ws);
+  if (!b->use_graph) return batch_eager(b, sys, mode, flags, wsc, st);
+  const size_t n = b->plans.size();
+  bool reuse = b->exec && same_systems(b->captured, sys, n) && b->captured_mode == mode &&
+               b->captured_flags == flags && b->captured_ws == ws && b->captured_stream == st;
+  if (!reuse) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    hipStream_t cs = st;
+    bool own = false;
+    if (cs == nullptr) {  // the legacy default stream cannot be captured
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return EXX_ERR_HIP;
+      own = true;
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      if (own) (void)hipStreamDestroy(cs);
+      return EXX_ERR_HIP;
+    }
+    int rc = batch_eager(b, sys, mode, flags, wsc, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (own) (void)hipStreamDestroy(cs);
+    if (rc != EXX_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return EXX_ERR_HIP;
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return EXX_ERR_HIP;
+    b->captured.assign(sys, sys + n);
+    b->captured_mode = mode;
+    b->captured_flags = flags;
+    b->captured_ws = ws;
+    b->captured_stream = st;
+  }
+  if (hipGraphLaunch(b->exec, st) != hipSuccess) return EXX_ERR_HIP;
+  return EXX_OK;
+}
+
+int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, double* kpsi,
+                 void* ws, size_t ws_bytes, void* stream, int budget_ms, const char* cache_path) {
+  if (!p || !psi || !occ || !kpsi) return EXX_ERR_INVALID_ARG;
+  (void)budget_ms;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return EXX_ERR_HIP;
+  std::ostringstream key;
+  key << prop.gcnArchName << " n=" << p->n << " bc=" << p->grid.bc << " prec=" << p->precision
+      << " N=" << n_orb;
+  // cache lookup
+  if (cache_path) {
+    std::ifstream f(cache_path);
+    std::string line;
+    while (std::getline(f, line)) {
+      auto bar = line.find('|');
+      if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
+      exx_tuning t{};
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d", &t.tile, &t.batch_slots, &t.zblock_a,
+                      &t.zblock_c) == 4)
+        return exx_plan_set_tuning(p, &t);
+    }
+  }
+  exx_tuning base = p->tuning, best = base;
+  float best_ms = 1e30f;
+  std::vector<int> tiles = {2, 4};
+  std::vector<int> batches = {32, 64, 128, 256, 1 << 20};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EXX_ERR_HIP;
+  double* ex_dev = nullptr;
+  if (hipMalloc((void**)&ex_dev, sizeof(double)) != hipSuccess) return EXX_ERR_HIP;
+  int rc = EXX_OK;
+  for (int t : tiles) {
+    for (int bs : batches) {
+      exx_tuning cand = base;
+      cand.tile = t;
+      cand.batch_slots = bs;
+      if (exx_plan_set_tuning(p, &cand) != EXX_OK) continue;
+      size_t need = 0;
+      if (exx_workspace_bytes(p, n_orb, &need) != EXX_OK || need > ws_bytes) continue;
+      if (exx_plan_prepare(p, n_orb) != EXX_OK) continue;
+      rc = exx_compute(p, psi, occ, n_orb, EXX_MODE_ENERGY_KPSI, 0, ex_dev, kpsi, nullptr, ws, ws_bytes, st);
+      if (rc != EXX_OK) break;
+      (void)hipEventRecord(e0, st);
+      const int reps = 3;
+      for (int r = 0; r < reps && rc == EXX_OK; ++r)
+        rc = exx_compute(p, psi, occ, n_orb, EXX_MODE_ENERGY_KPSI, 0, ex_dev, kpsi, nullptr, ws, ws_bytes, st);
+      (void)hipEventRecord(e1, st);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rc == EXX_OK && ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
+    }
+    if (rc != EXX_OK) break;
+  }
+  (void)hipFree(ex_dev);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  exx_plan_set_tuning(p, &best);
+  if (rc != EXX_OK) return rc;
+  if (cache_path) {
+    std::ofstream f(cache_path, std::ios::app);
+    f << key.str() << "|" << best.tile << " " << best.batch_slots << " " << best.zblock_a << " "
+      << best.zblock_c << "\n";
+  }
+  return exx_plan_prepare(p, n_orb);
+}
+
+}  // extern "C"

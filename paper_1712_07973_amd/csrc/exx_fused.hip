@@ -1,0 +1,781 @@
+// exx_fused.hip -- fused pair-build / FFT / Green multiply / reduction kernels.
+//
+// Work unit: a packed slot, two unordered orbital pairs whose real
+// co-densities rho_a = psi_ia psi_ja and rho_b = psi_ib psi_jb (Eq. 8 of
+// arXiv:1712.07973) travel as one complex field Z = rho_a + i rho_b.  The
+// Green's kernel is real and even, so the inverse transform returns
+// V_a + i V_b exactly.  Three passes per launch of slots:
+//
+//   pass A  pair build + forward x-transform of every grid row          -> X
+//   pass B  per x-frequency slab: forward y,z transforms, multiply by the
+//           kernel (Eq. 4 in Fourier space), inverse z,y transforms   X -> X
+//   pass C  inverse x-transform, then pair energies h^3 sum rho V (Eq. 5)
+//           and K psi accumulation (Eq. 3) over a tile of pairs, in FP64
+//
+// Free boundary (zero padding to 2n, Section 2.1.2) without materialising the
+// padded grid: the 2n-point transform of data supported on [0, n) splits by
+// the parity b of the output index into two n-point transforms of the input
+// modulated by w_2n^{b r}.  Per axis the padded problem is therefore 2
+// "classes" of n-point transforms; the x classes live in X (2 n^3 complex per
+// slot), the y/z classes are looped over inside pass B and summed after
+// demodulation.  Periodic grids have one class and no modulation.
+//
+// X layout per slot: [cx][kx][y][z] (z fastest), so pass B reads and writes
+// one contiguous n x n slab and passes A/C move rows of z-blocks.
+#include "exx_fft.hpp"
+#include "exx_internal.hpp"
+
+namespace exx {
+
+template <int N>
+struct SplitAC {  // x-lines of passes A and C: 16 work items per line in step 2
+  static constexpr int L2 = 16;
+  static constexpr int L1 = N / 16;
+  static_assert(L1 * L2 == N, "n must be a multiple of 16");
+};
+
+__device__ __forceinline__ int fold(int k, int M) { return k <= M - k ? k : M - k; }
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_convert(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) b[i] = (float)a[i];
+}
+
+__global__ void k_zero(double* __restrict__ p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = 0.0;
+}
+
+hipError_t launch_convert(const double* psi, float* psi32, size_t count, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 65536);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert, dim3(blocks), dim3(256), 0, s, psi, psi32, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, size_t count, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 65536);
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+__device__ __forceinline__ T sqrt_weight(const double* occ, int i, int j) {
+  double w = occ[i] * occ[j] * (i == j ? 1.0 : 2.0);
+  return (T)sqrt(w > 0.0 ? w : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// pass A: co-densities of two pairs packed as Z, forward x-transform per class
+// block: (y, z-block) x slot;  rows (y, z0..z0+ZB)
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NCLS, int ZB, int NT, bool W>
+__global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>* __restrict__ X,
+                                               const Slot* __restrict__ slots, int slot0,
+                                               const double* __restrict__ occ,
+                                               const cpx<T>* __restrict__ twg,
+                                               const cpx<T>* __restrict__ mdg) {
+  using S = SplitAC<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int P = N + 1;
+  constexpr int NL = NCLS * ZB;  // lines per block
+  __shared__ cpx<T> zb[ZB * P];
+  __shared__ cpx<T> wk[NL * P];
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+
+  const int tid = threadIdx.x;
+  const int y = blockIdx.x / (N / ZB);
+  const int z0 = (blockIdx.x % (N / ZB)) * ZB;
+  const int ls = blockIdx.y;
+  const Slot sl = slots[slot0 + ls];
+  const size_t M3 = (size_t)N * N * N;
+
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    if (NCLS == 2) md[k] = mdg[k];
+  }
+  T wa = T(1), wb = T(1);
+  if (W) {
+    wa = sqrt_weight<T>(occ, sl.ia, sl.ja);
+    if (sl.ib >= 0) wb = sqrt_weight<T>(occ, sl.ib, sl.jb);
+  }
+  const T* pia = psi + (size_t)sl.ia * M3;
+  const T* pja = psi + (size_t)sl.ja * M3;
+  const T* pib = psi + (size_t)(sl.ib >= 0 ? sl.ib : 0) * M3;
+  const T* pjb = psi + (size_t)(sl.ib >= 0 ? sl.jb : 0) * M3;
+  const bool hb = sl.ib >= 0;
+  for (int p = tid; p < ZB * N; p += NT) {
+    int zi = p / N, x = p % N;
+    size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
+    T a = pia[o] * pja[o] * wa;
+    T b = hb ? pib[o] * pjb[o] * wb : T(0);
+    zb[zi * P + x] = {a, b};
+  }
+  __syncthreads();
+
+  // step 1: items (line, t), line = cx*ZB + zi fastest
+  constexpr int C1 = NL * L2;
+#pragma unroll
+  for (int it0 = 0; it0 < C1; it0 += NT) {
+    int it = it0 + tid;
+    if (C1 % NT == 0 || it < C1) {
+      int line = it % NL, t = it / NL;
+      int cx = line / ZB, zi = line % ZB;
+      cpx<T> v[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        int x = t + L2 * k1;
+        v[k1] = zb[zi * P + x];
+        if (NCLS == 2 && cx == 1) v[k1] = cmul(v[k1], md[x]);
+      }
+      Dft<L1, -1, T>::run(v);
+#pragma unroll
+      for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+      for (int q1 = 0; q1 < L1; ++q1) wk[line * P + t + L2 * q1] = v[q1];
+    }
+  }
+  __syncthreads();
+
+  // step 2: items (line, q1); DFT_L2 over t -> kx = q1 + L1 q2, written to X
+  constexpr int C2 = NL * L1;
+  cpx<T>* Xs = X + (size_t)ls * NCLS * M3;
+#pragma unroll
+  for (int it0 = 0; it0 < C2; it0 += NT) {
+    int it = it0 + tid;
+    if (C2 % NT == 0 || it < C2) {
+      int line = it % NL, q1 = it / NL;
+      int cx = line / ZB, zi = line % ZB;
+      cpx<T> v[L2];
+#pragma unroll
+      for (int t = 0; t < L2; ++t) v[t] = wk[line * P + t + L2 * q1];
+      Dft<L2, -1, T>::run(v);
+#pragma unroll
+      for (int q2 = 0; q2 < L2; ++q2) {
+        int kx = q1 + L1 * q2;
+        Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi] = v[q2];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass B: per (slot, cx, kx) slab [y][z]: 2-D forward transform per (cy, cz)
+// class, kernel multiply, 2-D inverse transform, demodulate and sum classes.
+// Energy-only variant: accumulate sum_k K |Z|^2 (Parseval) instead.
+// LDS layouts: A = [y][z] (pitch N), B = [z][y] (pitch N+1), same storage.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NCLS, int NT, bool EONLY>
+__global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* __restrict__ ktab,
+                                               const cpx<T>* __restrict__ twg,
+                                               const cpx<T>* __restrict__ mdg,
+                                               double* __restrict__ e_slot, int slot0) {
+  using S = Split<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int PB = N + 1;
+  constexpr int M = NCLS * N;
+  constexpr int H = M / 2 + 1;
+  __shared__ cpx<T> lds[N * PB];
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+
+  const int tid = threadIdx.x;
+  const int slab = blockIdx.x;  // cx * N + kx
+  const int ls = blockIdx.y;
+  const int cx = slab / N, kxp = slab % N;
+  const int kxf = NCLS == 2 ? 2 * kxp + cx : kxp;
+  const T* kt = ktab + (size_t)fold(kxf, M) * H * H;
+  cpx<T>* g = X + ((size_t)ls * NCLS * N + slab) * (size_t)(N * N);
+
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    if (NCLS == 2) md[k] = mdg[k];
+  }
+
+  constexpr int C1 = N * L2;  // items (line, t)
+  constexpr int C2 = N * L1;  // items (line, q1)
+  constexpr int I1 = (C1 + NT - 1) / NT;
+  constexpr int I2 = (C2 + NT - 1) / NT;
+
+  cpx<T> xin[I1][L1];
+  cpx<T> acc[I1][L1];
+#pragma unroll
+  for (int ii = 0; ii < I1; ++ii) {
+    int it = tid + ii * NT;
+    if (C1 % NT == 0 || it < C1) {
+      int z = it % N, t = it / N;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        xin[ii][k1] = g[(t + L2 * k1) * N + z];
+        acc[ii][k1] = {T(0), T(0)};
+      }
+    }
+  }
+  double esum = 0.0;
+  __syncthreads();
+
+#pragma unroll 1
+  for (int cls = 0; cls < NCLS * NCLS; ++cls) {
+    const int cy = NCLS == 2 ? (cls >> 1) : 0;
+    const int cz = NCLS == 2 ? (cls & 1) : 0;
+    // step 1: y forward, items (z, t): reads input, writes layout A
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (C1 % NT == 0 || it < C1) {
+        int z = it % N, t = it / N;
+        cpx<T> v[L1];
+        cpx<T> mz = (NCLS == 2 && cz) ? md[z] : cpx<T>{T(1), T(0)};
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) {
+          cpx<T> a = xin[ii][k1];
+          if (NCLS == 2 && cy) a = cmul(a, md[t + L2 * k1]);
+          if (NCLS == 2 && cz) a = cmul(a, mz);
+          v[k1] = a;
+        }
+        Dft<L1, -1, T>::run(v);
+#pragma unroll
+        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * N + z] = v[q1];
+      }
+    }
+    __syncthreads();
+    // step 2: y forward, items (z, q1): layout A -> layout B (ky natural order)
+    {
+      cpx<T> w[I2][L2];
+#pragma unroll
+      for (int ii = 0; ii < I2; ++ii) {
+        int it = tid + ii * NT;
+        if (C2 % NT == 0 || it < C2) {
+          int z = it % N, q1 = it / N;
+#pragma unroll
+          for (int t = 0; t < L2; ++t) w[ii][t] = lds[(t + L2 * q1) * N + z];
+          Dft<L2, -1, T>::run(w[ii]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ii = 0; ii < I2; ++ii) {
+        int it = tid + ii * NT;
+        if (C2 % NT == 0 || it < C2) {
+          int z = it % N, q1 = it / N;
+#pragma unroll
+          for (int q2 = 0; q2 < L2; ++q2) lds[z * PB + q1 + L1 * q2] = w[ii][q2];
+        }
+      }
+    }
+    __syncthreads();
+    // step 3: z forward step 1, items (ky, t), in place in layout B
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (C1 % NT == 0 || it < C1) {
+        int ky = it % N, t = it / N;
+        cpx<T> v[L1];
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) v[k1] = lds[(t + L2 * k1) * PB + ky];
+        Dft<L1, -1, T>::run(v);
+#pragma unroll
+        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * PB + ky] = v[q1];
+      }
+    }
+    __syncthreads();
+    // step 4: z forward step 2 -> spectrum, kernel multiply, inverse step 2
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (C2 % NT == 0 || it < C2) {
+        int ky = it % N, q1 = it / N;
+        cpx<T> v[L2];
+#pragma unroll
+        for (int t = 0; t < L2; ++t) v[t] = lds[(t + L2 * q1) * PB + ky];
+        Dft<L2, -1, T>::run(v);
+        const int kyf = NCLS == 2 ? 2 * ky + cy : ky;
+        const T* kr = kt + (size_t)fold(kyf, M) * H;
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) {
+          int kz = q1 + L1 * q2;
+          int kzf = NCLS == 2 ? 2 * kz + cz : kz;
+          T kv = kr[fold(kzf, M)];
+          if (EONLY) {
+            esum += (double)kv * ((double)v[q2].x * (double)v[q2].x +
+                                  (double)v[q2].y * (double)v[q2].y);
+          } else {
+            v[q2].x *= kv;
+            v[q2].y *= kv;
+          }
+        }
+        if (!EONLY) {
+          Dft<L2, 1, T>::run(v);
+#pragma unroll
+          for (int t = 1; t < L2; ++t) v[t] = cmulc(v[t], tw[t * q1]);
+#pragma unroll
+          for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * PB + ky] = v[t];
+        }
+      }
+    }
+    __syncthreads();
+    if (EONLY) continue;
+    // step 5: z inverse step 1, items (ky, t), in place
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (C1 % NT == 0 || it < C1) {
+        int ky = it % N, t = it / N;
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * PB + ky];
+        Dft<L1, 1, T>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) lds[(t + L2 * k1) * PB + ky] = v[k1];
+      }
+    }
+    __syncthreads();
+    // step 6: y inverse step 2, items (z, q1): layout B -> layout A
+    {
+      cpx<T> w[I2][L2];
+#pragma unroll
+      for (int ii = 0; ii < I2; ++ii) {
+        int it = tid + ii * NT;
+        if (C2 % NT == 0 || it < C2) {
+          int z = it % N, q1 = it / N;
+#pragma unroll
+          for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = lds[z * PB + q1 + L1 * q2];
+          Dft<L2, 1, T>::run(w[ii]);
+#pragma unroll
+          for (int t = 1; t < L2; ++t) w[ii][t] = cmulc(w[ii][t], tw[t * q1]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ii = 0; ii < I2; ++ii) {
+        int it = tid + ii * NT;
+        if (C2 % NT == 0 || it < C2) {
+          int z = it % N, q1 = it / N;
+#pragma unroll
+          for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * N + z] = w[ii][t];
+        }
+      }
+    }
+    __syncthreads();
+    // step 7: y inverse step 1, items (z, t): demodulate and accumulate
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (C1 % NT == 0 || it < C1) {
+        int z = it % N, t = it / N;
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * N + z];
+        Dft<L1, 1, T>::run(v);
+        cpx<T> mz = (NCLS == 2 && cz) ? md[z] : cpx<T>{T(1), T(0)};
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) {
+          cpx<T> a = v[k1];
+          if (NCLS == 2 && cy) a = cmulc(a, md[t + L2 * k1]);
+          if (NCLS == 2 && cz) a = cmulc(a, mz);
+          acc[ii][k1] = cadd(acc[ii][k1], a);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (EONLY) {
+    // block reduction of the Parseval sum, one atomic per block
+    __shared__ double red[NT / 64];
+    double v = esum;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < NT / 64; ++w) s += red[w];
+      atomicAdd(&e_slot[2 * (slot0 + ls)], s);
+    }
+    return;
+  }
+#pragma unroll
+  for (int ii = 0; ii < I1; ++ii) {
+    int it = tid + ii * NT;
+    if (C1 % NT == 0 || it < C1) {
+      int z = it % N, t = it / N;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) g[(t + L2 * k1) * N + z] = acc[ii][k1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pass C: inverse x-transform of every slot of a pair tile for rows
+// (y, z0..z0+ZB), then FP64 pair energies and K psi accumulation.
+// Each thread owns fixed grid points; the tile's orbitals are staged in LDS
+// (FP32/FP64 copies of psi) and the K psi partial sums kept in LDS in FP64,
+// flushed once per tile with FP64 atomics.
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NCLS, int ZB, int NT, int TMAX>
+__global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
+                                               const T* __restrict__ psi,
+                                               const double* __restrict__ occ,
+                                               const Slot* __restrict__ slots,
+                                               const TilePair* __restrict__ tiles, int t0,
+                                               int slot_base, double* __restrict__ kpsi,
+                                               double* __restrict__ e_slot, int want_k,
+                                               int want_e, const cpx<T>* __restrict__ twg,
+                                               const cpx<T>* __restrict__ mdg) {
+  using S = SplitAC<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int P = N + 1;
+  constexpr int NL = NCLS * ZB;
+  constexpr int NP = ZB * N;       // points per block
+  constexpr int NI = ZB * L2;      // point-owner items (zi, t), zi fastest
+  constexpr int NO = 2 * TMAX;     // orbitals per tile (I then J)
+  static_assert(NI == NT, "one point-owner item per thread");
+  __shared__ cpx<T> xs[NL * P];
+  __shared__ T ps[NO * NP];
+  __shared__ double acc[NO * NP];
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+
+  const int tid = threadIdx.x;
+  const int y = blockIdx.x / (N / ZB);
+  const int z0 = (blockIdx.x % (N / ZB)) * ZB;
+  const TilePair tp = tiles[t0 + blockIdx.y];
+  const size_t M3 = (size_t)N * N * N;
+  const int nloc = tp.diag ? tp.nI : TMAX + tp.nJ;
+
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    if (NCLS == 2) md[k] = mdg[k];
+  }
+  // point index of (zi, t, k1): pt = k1 * NI + t * ZB + zi; x = t + L2 k1
+  // stage psi of the tile's orbitals (coalesced along x) and clear acc
+  for (int lo = 0; lo < nloc; ++lo) {
+    if (!tp.diag && lo >= tp.nI && lo < TMAX) continue;
+    int o = lo < TMAX ? tp.I0 + lo : tp.J0 + (lo - TMAX);
+    const T* po = psi + (size_t)o * M3;
+    for (int p = tid; p < NP; p += NT) {
+      int x = p % N, zi = p / N;
+      int t = x % L2, k1 = x / L2;
+      int pt = k1 * NI + t * ZB + zi;
+      ps[lo * NP + pt] = po[((size_t)(z0 + zi) * N + y) * N + x];
+      acc[lo * NP + pt] = 0.0;
+    }
+  }
+  __syncthreads();
+
+  const int zi_own = tid % ZB, t_own = tid / ZB;
+
+#pragma unroll 1
+  for (int s = tp.s0; s < tp.s1; ++s) {
+    const Slot sl = slots[s];
+    const cpx<T>* Xs = X + (size_t)(s - slot_base) * NCLS * M3;
+    for (int p = tid; p < NCLS * N * ZB; p += NT) {
+      int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
+      xs[(cx * ZB + zi) * P + kx] = Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi];
+    }
+    __syncthreads();
+    // inverse step 2 (per q1): IDFT_L2 over q2, conj twiddle
+    constexpr int C2 = NL * L1;
+    constexpr int I2 = (C2 + NT - 1) / NT;
+    cpx<T> w[I2][L2];
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (C2 % NT == 0 || it < C2) {
+        int line = it % NL, q1 = it / NL;
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = xs[line * P + q1 + L1 * q2];
+        Dft<L2, 1, T>::run(w[ii]);
+#pragma unroll
+        for (int t = 1; t < L2; ++t) w[ii][t] = cmulc(w[ii][t], tw[t * q1]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (C2 % NT == 0 || it < C2) {
+        int line = it % NL, q1 = it / NL;
+#pragma unroll
+        for (int t = 0; t < L2; ++t) xs[line * P + t + L2 * q1] = w[ii][t];
+      }
+    }
+    __syncthreads();
+    // inverse step 1 (per t) for both x classes, demodulate: V_a + i V_b
+    cpx<T> V[L1];
+    {
+      cpx<T> v[L1];
+#pragma unroll
+      for (int q1 = 0; q1 < L1; ++q1) v[q1] = xs[zi_own * P + t_own + L2 * q1];
+      Dft<L1, 1, T>::run(v);
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) V[k1] = v[k1];
+      if (NCLS == 2) {
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xs[(ZB + zi_own) * P + t_own + L2 * q1];
+        Dft<L1, 1, T>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
+      }
+    }
+    // reductions at the owned points
+    const bool hb = sl.ib >= 0;
+    // local orbital slot: I block first; J block at TMAX (I and J disjoint off the diagonal)
+    auto loc = [&](int o) { return (o >= tp.I0 && o < tp.I0 + tp.nI) ? o - tp.I0 : TMAX + (o - tp.J0); };
+    const int la_i = loc(sl.ia), la_j = loc(sl.ja);
+    const int lb_i = hb ? loc(sl.ib) : 0, lb_j = hb ? loc(sl.jb) : 0;
+    const double fa_i = occ[sl.ia], fa_j = occ[sl.ja];
+    const double fb_i = hb ? occ[sl.ib] : 0.0, fb_j = hb ? occ[sl.jb] : 0.0;
+    double ea = 0.0, eb = 0.0;
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) {
+      const int pt = k1 * NI + tid;
+      const double Va = (double)V[k1].x, Vb = (double)V[k1].y;
+      const T pai = ps[la_i * NP + pt], paj = ps[la_j * NP + pt];
+      ea += (double)(pai * paj) * Va;
+      if (want_k) {
+        acc[la_i * NP + pt] += fa_j * Va * (double)paj;
+        if (sl.ia != sl.ja) acc[la_j * NP + pt] += fa_i * Va * (double)pai;
+      }
+      if (hb) {
+        const T pbi = ps[lb_i * NP + pt], pbj = ps[lb_j * NP + pt];
+        eb += (double)(pbi * pbj) * Vb;
+        if (want_k) {
+          acc[lb_i * NP + pt] += fb_j * Vb * (double)pbj;
+          if (sl.ib != sl.jb) acc[lb_j * NP + pt] += fb_i * Vb * (double)pbi;
+        }
+      }
+    }
+    if (want_e) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        ea += __shfl_xor(ea, off);
+        eb += __shfl_xor(eb, off);
+      }
+      if ((tid & 63) == 0) {
+        atomicAdd(&e_slot[2 * s], ea);
+        if (hb) atomicAdd(&e_slot[2 * s + 1], eb);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (!want_k) return;
+  // flush: coalesced FP64 atomics along x
+  for (int lo = 0; lo < nloc; ++lo) {
+    if (!tp.diag && lo >= tp.nI && lo < TMAX) continue;
+    int o = lo < TMAX ? tp.I0 + lo : tp.J0 + (lo - TMAX);
+    double* ko = kpsi + (size_t)o * M3;
+    for (int p = tid; p < NP; p += NT) {
+      int x = p % N, zi = p / N;
+      int t = x % L2, k1 = x / L2;
+      int pt = k1 * NI + t * ZB + zi;
+      atomicAdd(&ko[((size_t)(z0 + zi) * N + y) * N + x], acc[lo * NP + pt]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// finalize: E_x = -1/2 sum_ij f_i f_j e_ij in a fixed order, pair-energy matrix
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_finalize(const Slot* __restrict__ slots, int nslots,
+                                                   const double* __restrict__ occ,
+                                                   const double* __restrict__ e_slot, int n_orb,
+                                                   double h3, int packed_energy,
+                                                   double* __restrict__ ex_out,
+                                                   double* __restrict__ pair_e) {
+  __shared__ double red[16];
+  const int tid = threadIdx.x;
+  double sum = 0.0;
+  for (int s = tid; s < nslots; s += 1024) {
+    const Slot sl = slots[s];
+    if (packed_energy) {
+      sum += h3 * e_slot[2 * s];
+      continue;
+    }
+    for (int half = 0; half < 2; ++half) {
+      int i = half ? sl.ib : sl.ia, j = half ? sl.jb : sl.ja;
+      if (i < 0) continue;
+      double e = h3 * e_slot[2 * s + half];
+      sum += occ[i] * occ[j] * (i == j ? 1.0 : 2.0) * e;
+      if (pair_e) {
+        pair_e[(size_t)i * n_orb + j] = e;
+        pair_e[(size_t)j * n_orb + i] = e;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if ((tid & 63) == 0) red[tid >> 6] = sum;
+  __syncthreads();
+  if (tid == 0 && ex_out) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += red[w];
+    *ex_out = -0.5 * s;
+  }
+}
+
+hipError_t launch_finalize(const Slot* slots, int nslots, const double* occ, const double* e_slot,
+                           int n_orb, double h3, bool packed_energy, double* ex_out,
+                           double* pair_e, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, slots, nslots, occ, e_slot, n_orb, h3,
+                     packed_energy ? 1 : 0, ex_out, pair_e);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// host dispatch over the supported grid sizes
+// ---------------------------------------------------------------------------
+template <typename F>
+static hipError_t dispatch_n(int n, F&& f) {
+  switch (n) {
+    case 16: return f.template operator()<16>();
+    case 32: return f.template operator()<32>();
+    case 48: return f.template operator()<48>();
+    case 64: return f.template operator()<64>();
+    case 80: return f.template operator()<80>();
+    case 96: return f.template operator()<96>();
+    case 112: return f.template operator()<112>();
+    case 128: return f.template operator()<128>();
+    default: return hipErrorInvalidValue;
+  }
+}
+
+bool fused_supported(int precision, int n) {
+  if (n % 16 != 0 || n < 16 || n > 128) return false;
+  if (precision == EXX_PREC_FP64_FUSED) return n <= 96;
+  return true;
+}
+
+template <typename T, int N>
+constexpr int pass_b_threads() {
+  // enough threads for a few items each; LDS bounds one block per CU at large N
+  return N <= 32 ? 128 : (N <= 64 ? 256 : 512);
+}
+
+template <typename T>
+hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slots, int slot0,
+                         int nslots, const double* occ, bool weighted, int zb, const Tables& tb) {
+  if (nslots <= 0) return hipSuccess;
+  return dispatch_n(L.n, [&]<int N>() -> hipError_t {
+    constexpr int ZB = 16;
+    constexpr int NT = 256;
+    (void)zb;
+    dim3 grid(N * (N / ZB), nslots);
+    auto* Xc = static_cast<cpx<T>*>(X);
+    auto* tw = static_cast<const cpx<T>*>(tb.tw);
+    auto* md = static_cast<const cpx<T>*>(tb.md);
+    if (L.ncls == 2) {
+      if (weighted)
+        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, true>), grid, dim3(NT), 0, L.stream, psi,
+                           Xc, slots, slot0, occ, tw, md);
+      else
+        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, false>), grid, dim3(NT), 0, L.stream, psi,
+                           Xc, slots, slot0, occ, tw, md);
+    } else {
+      if (weighted)
+        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, true>), grid, dim3(NT), 0, L.stream, psi,
+                           Xc, slots, slot0, occ, tw, md);
+      else
+        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, false>), grid, dim3(NT), 0, L.stream, psi,
+                           Xc, slots, slot0, occ, tw, md);
+    }
+    return hipGetLastError();
+  });
+}
+
+template <typename T>
+hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
+                         int slot0, const Tables& tb) {
+  if (nslots <= 0) return hipSuccess;
+  return dispatch_n(L.n, [&]<int N>() -> hipError_t {
+    if constexpr (sizeof(T) == 8 && N > 96) {
+      return hipErrorInvalidValue;
+    } else {
+      constexpr int NT = pass_b_threads<T, N>();
+      auto* Xc = static_cast<cpx<T>*>(X);
+      auto* kt = static_cast<const T*>(tb.ktab);
+      auto* tw = static_cast<const cpx<T>*>(tb.tw);
+      auto* md = static_cast<const cpx<T>*>(tb.md);
+      if (L.ncls == 2) {
+        dim3 grid(2 * N, nslots);
+        if (energy_only)
+          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, true>), grid, dim3(NT), 0, L.stream, Xc, kt,
+                             tw, md, e_slot, slot0);
+        else
+          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, false>), grid, dim3(NT), 0, L.stream, Xc,
+                             kt, tw, md, e_slot, slot0);
+      } else {
+        dim3 grid(N, nslots);
+        if (energy_only)
+          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, true>), grid, dim3(NT), 0, L.stream, Xc, kt,
+                             tw, md, e_slot, slot0);
+        else
+          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, false>), grid, dim3(NT), 0, L.stream, Xc,
+                             kt, tw, md, e_slot, slot0);
+      }
+      return hipGetLastError();
+    }
+  });
+}
+
+template <typename T>
+hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
+                         const Slot* slots, const TilePair* tiles, int t0, int ntiles,
+                         int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
+                         int zb, int tmax, const Tables& tb) {
+  if (ntiles <= 0) return hipSuccess;
+  (void)zb;
+  return dispatch_n(L.n, [&]<int N>() -> hipError_t {
+    if constexpr (sizeof(T) == 8 && N > 96) {
+      return hipErrorInvalidValue;
+    } else {
+    constexpr int ZB = 8;
+    constexpr int NT = ZB * 16;
+    dim3 grid(N * (N / ZB), ntiles);
+    auto* Xc = static_cast<const cpx<T>*>(X);
+    auto* tw = static_cast<const cpx<T>*>(tb.tw);
+    auto* md = static_cast<const cpx<T>*>(tb.md);
+    if (tmax > 4) return hipErrorInvalidValue;
+    if (L.ncls == 2)
+      hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, 4>), grid, dim3(NT), 0, L.stream, Xc, psi,
+                         occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
+                         want_e ? 1 : 0, tw, md);
+    else
+      hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, 4>), grid, dim3(NT), 0, L.stream, Xc, psi,
+                         occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
+                         want_e ? 1 : 0, tw, md);
+    return hipGetLastError();
+    }
+  });
+}
+
+template hipError_t launch_pass_a<float>(const Launch&, const float*, void*, const Slot*, int, int,
+                                         const double*, bool, int, const Tables&);
+template hipError_t launch_pass_a<double>(const Launch&, const double*, void*, const Slot*, int,
+                                          int, const double*, bool, int, const Tables&);
+template hipError_t launch_pass_b<float>(const Launch&, void*, int, bool, double*, int,
+                                         const Tables&);
+template hipError_t launch_pass_b<double>(const Launch&, void*, int, bool, double*, int,
+                                          const Tables&);
+template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
+                                         const Slot*, const TilePair*, int, int, int, double*,
+                                         double*, bool, bool, int, int, const Tables&);
+template hipError_t launch_pass_c<double>(const Launch&, const void*, const double*,
+                                          const double*, const Slot*, const TilePair*, int, int,
+                                          int, double*, double*, bool, bool, int, int,
+                                          const Tables&);
+
+}  // namespace exx

@@ -1,0 +1,108 @@
+// exx_internal.hpp -- host-side plan structures and kernel launch interfaces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/exx.h"
+
+namespace exx {
+
+// One packed slot = two unordered pairs (ia, ja) and (ib, jb) sharing one
+// complex transform (real part: pair a, imaginary part: pair b); ib < 0 marks
+// an empty second half.  Slots are grouped by pair tile.
+struct Slot {
+  int ia, ja, ib, jb;
+};
+
+// One pair tile: orbitals [I0, I0+nI) x [J0, J0+nJ) (upper triangle when
+// diag), its slots [s0, s1).
+struct TilePair {
+  int s0, s1, I0, nI, J0, nJ, diag, pad;
+};
+
+struct Schedule {
+  int n_orb = 0;
+  int tile = 0;
+  int batch_slots = 0;
+  long long n_pairs = 0;
+  std::vector<Slot> slots;
+  std::vector<TilePair> tiles;
+  // launch chunks: [tile_begin, tile_end) with slots [slot_begin, slot_end)
+  struct Chunk {
+    int t0, t1, s0, s1;
+  };
+  std::vector<Chunk> chunks;
+  Slot* d_slots = nullptr;
+  TilePair* d_tiles = nullptr;
+};
+
+// Device tables of one plan (precision-specific arrays are null when unused).
+struct Tables {
+  void* tw = nullptr;      // w_n^k, k < n (fused paths), cpx<T>
+  void* md = nullptr;      // w_{2n}^r, r < n (free boundary modulation), cpx<T>
+  void* ktab = nullptr;    // kernel octant / (fft points), T, [(m/2+1)^3]
+  void* tw_m = nullptr;    // w_m^k, k < m (plain path), cpx<double>
+  void* ktab_m = nullptr;  // kernel octant / m^3 for the plain path, double
+};
+
+struct Launch {
+  int n, ncls, m;  // grid, x-classes (1 periodic, 2 free), fft points per axis
+  double h3;       // volume element
+  hipStream_t stream;
+};
+
+}  // namespace exx
+
+struct exx_plan {
+  exx_grid grid;
+  int n = 0, m = 0, ncls = 1;
+  double h3 = 0, R = 0;
+  int precision = 0;
+  int n_orb_max = 0;
+  int device = 0;
+  exx_tuning tuning{};
+  exx::Tables tables;
+  std::map<int, exx::Schedule> schedules;  // keyed by n_orb (schedule depends on tuning.tile)
+};
+
+namespace exx {
+
+// ---- fused kernels (FP32 and FP64 instantiations), exx_fused.hip ----------
+// All return hipSuccess or the launch error.
+hipError_t launch_convert(const double* psi, float* psi32, size_t count, hipStream_t s);
+hipError_t launch_zero(double* p, size_t count, hipStream_t s);
+
+template <typename T>
+hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slots, int slot0,
+                         int nslots, const double* occ, bool weighted, int zb, const Tables& tb);
+template <typename T>
+hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
+                         int slot0, const Tables& tb);
+template <typename T>
+hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
+                         const Slot* slots, const TilePair* tiles, int t0, int ntiles,
+                         int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
+                         int zb, int tmax, const Tables& tb);
+hipError_t launch_finalize(const Slot* slots, int nslots, const double* occ, const double* e_slot,
+                           int n_orb, double h3, bool packed_energy, double* ex_out,
+                           double* pair_e, hipStream_t s);
+
+bool fused_supported(int precision, int n);
+
+// ---- plain FP64 path, exx_plain.hip ---------------------------------------
+hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs_in_launch,
+                       int n, int m, void* Z, hipStream_t s);
+hipError_t plain_fft_axis(void* Z, int npairs, int m, int axis, int dir, const Tables& tb,
+                          hipStream_t s);
+hipError_t plain_kernel_mul(void* Z, int npairs, int m, const Tables& tb, hipStream_t s);
+hipError_t plain_reduce(const void* Z, const double* psi, const double* occ, const Slot* slots,
+                        int slot0, int npairs_in_launch, int n, int m, double h3, double* kpsi,
+                        double* e_slot, bool want_k, bool want_e, hipStream_t s);
+
+}  // namespace exx

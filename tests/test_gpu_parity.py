@@ -1,0 +1,107 @@
+"""GPU parity: the HIP paths (through the C ABI) against the FP64 oracle.
+
+Sizes span several pair tiles with a ragged last tile (N not a multiple of
+the tile edge), an odd number of pairs (a half-filled packed slot), both
+boundary conditions and the mixed radices 3, 5 and 7 of the supported grids.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import (TOL_FP32_E_PER_ORB, TOL_FP32_K, TOL_FP64_E, TOL_FP64_K, grid_of,
+                        kpsi_rel_err, oracle_result, say)
+
+pytestmark = pytest.mark.gpu
+
+exx = pytest.importorskip("paper_1712_07973_amd")
+
+CASES = [
+    # (bc, n, N, seed, frac)
+    ("periodic", 16, 3, 21, 0),
+    ("free", 16, 5, 22, 1),
+    ("periodic", 32, 8, 1001, 0),
+    ("free", 32, 6, 23, 0),
+    ("periodic", 48, 5, 24, 0),
+    ("free", 48, 3, 25, 0),
+    ("periodic", 80, 3, 26, 0),
+    ("free", 16, 9, 27, 2),
+]
+
+
+def run(s, precision, pair_e=True):
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    plan = exx.Plan(grid_of(s), precision, n_orb_max=s.n_orb)
+    pe = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=dev) if pair_e else None
+    ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)
+    torch.cuda.synchronize()
+    return float(ex.item()), kpsi.cpu().numpy(), (pe.cpu().numpy() if pe is not None else None)
+
+
+@pytest.mark.parametrize("precision", ["fp64_plain", "fp64_fused"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}{c[1]}_N{c[2]}")
+def test_fp64_paths_match_oracle(case, precision):
+    bc, n, N, seed, frac = case
+    say(f"[parity] {precision} {bc} n={n} N={N} seed={seed}")
+    s, ref = oracle_result(bc, n, N, seed, frac)
+    E, K, P = run(s, precision)
+    assert abs(E - ref["E"]) <= TOL_FP64_E * abs(ref["E"])
+    assert kpsi_rel_err(K, ref["kpsi"]) <= TOL_FP64_K
+    assert np.max(np.abs(P - ref["pair_e"])) <= 1e-12 * np.max(np.abs(ref["pair_e"]))
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}{c[1]}_N{c[2]}")
+def test_fp32_path_within_tolerance(case):
+    bc, n, N, seed, frac = case
+    say(f"[parity] fp32 {bc} n={n} N={N} seed={seed}")
+    s, ref = oracle_result(bc, n, N, seed, frac)
+    E, K, P = run(s, "fp32")
+    assert abs(E - ref["E"]) / N < TOL_FP32_E_PER_ORB
+    assert kpsi_rel_err(K, ref["kpsi"]) < TOL_FP32_K
+    assert np.max(np.abs(P - ref["pair_e"])) <= 1e-6 * np.max(np.abs(ref["pair_e"]))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
+def test_energy_only_and_kpsi_only_modes(precision):
+    say(f"[modes] {precision}")
+    s, ref = oracle_result("free", 32, 6, 23, 0)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    plan = exx.Plan(grid_of(s), precision, n_orb_max=8)
+    ex, _, _ = plan.compute(psi, occ, "energy")  # Parseval route on the fused paths
+    _, kpsi, _ = plan.compute(psi, occ, "kpsi")
+    torch.cuda.synchronize()
+    tolE = TOL_FP64_E if precision != "fp32" else 1e-6 * 6 / abs(ref["E"])
+    assert abs(ex.item() - ref["E"]) <= tolE * abs(ref["E"])
+    tolK = TOL_FP64_K if precision != "fp32" else TOL_FP32_K
+    assert kpsi_rel_err(kpsi.cpu().numpy(), ref["kpsi"]) <= tolK
+
+
+def test_accumulate_flag_adds_into_kpsi():
+    say("[accumulate] fp32")
+    s, ref = oracle_result("periodic", 16, 3, 21, 0)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    plan = exx.Plan(grid_of(s), "fp32", n_orb_max=4)
+    k0 = torch.ones_like(psi)
+    plan.compute(psi, occ, "kpsi", kpsi=k0, accumulate=True)
+    torch.cuda.synchronize()
+    assert kpsi_rel_err(k0.cpu().numpy() - 1.0, ref["kpsi"]) < TOL_FP32_K
+
+
+def test_workspace_too_small_is_rejected():
+    say("[workspace] fp32")
+    s, _ = oracle_result("periodic", 16, 3, 21, 0)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    plan = exx.Plan(grid_of(s), "fp32", n_orb_max=4)
+    small = torch.empty(1024, dtype=torch.uint8, device=dev)
+    with pytest.raises(RuntimeError, match="WORKSPACE"):
+        plan.compute(psi, occ, "energy_kpsi", workspace=small)
+    with pytest.raises(RuntimeError, match="CAPACITY"):
+        big = torch.zeros((5, 16, 16, 16), dtype=torch.float64, device=dev)
+        plan.compute(big, torch.ones(5, dtype=torch.float64, device=dev), "energy_kpsi")
