@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of the exact-exchange hot path on one MI355X.
+
+One step = one full evaluation of E_x and K psi (pair build, forward
+transforms, kernel multiply, inverse transforms, FP64 pair energies and
+K psi) for every orbital pair of one synthetic system, with inputs already
+resident in HBM.  Workload: isolated system, 64^3 grid zero-padded to 128^3,
+h = 0.4 bohr, 32 Loewdin-orthonormalised Gaussian orbitals with occupation 2,
+truncated Coulomb kernel with R = L, i.e. 528 pair Poisson solves per step.
+
+Prints one JSON line: pair-solves/s of the FP32 path (value), the plain FP64
+GPU path and the FP64 fused ablation beside it, per-pass device times from
+hipEvents recorded on the compute stream, the roofline of the dominant
+kernel, the accuracy against the plain FP64 path, and the FP64 CPU oracle's
+rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, datasheet
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X vector FP32, datasheet
+METRIC = "orbital-pair Poisson solves/s (E_x+Kψ) FP32-batched vs FP64, HBM GB/s"
+
+
+def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int) -> dict:
+    """Minimum HBM bytes of each pass of one evaluation (FP32 path).
+
+    Per packed slot the spectrum X holds ncls * n^3 complex FP32 values:
+    pass A writes it, pass B reads and rewrites it, pass C reads it.  The
+    orbitals (FP32 copy) are read once by A and once by C; K psi (FP64) is
+    written once.  Pass B's kernel table is shared by all slots (cache
+    resident) and not counted.
+    """
+    x = ncls * n ** 3 * 8
+    orb32 = n_orb * n ** 3 * 4
+    kps = n_orb * n ** 3 * 8
+    return {
+        "convert": n_orb * n ** 3 * (8 + 4),
+        "pass_a": n_slots * x + orb32,
+        "pass_b": n_slots * 2 * x,
+        "pass_c": n_slots * x + orb32 + kps,
+    }
+
+
+def fft_flops(n: int, ncls: int, n_slots: int, share_y: bool) -> dict:
+    """Nominal 5 L log2 L flops per complex n-point line transform, per pass.
+
+    Pass A/C: ncls x-classes of n^2 lines.  Pass B, per slab of n^2 points:
+    with shared y-transforms ncls y-lines sets forward and inverse plus ncls^2
+    z-line sets forward and inverse (2n ncls (1 + ncls) lines), otherwise
+    4 n ncls^2 lines.
+    """
+    f = 5.0 * n * math.log2(n)
+    a = n_slots * ncls * n * n * f
+    per_slab = 2 * n * ncls * (1 + ncls) if share_y else 4 * n * ncls * ncls
+    b = n_slots * ncls * n * per_slab * f
+    c = n_slots * ncls * n * n * f
+    return {"pass_a": a, "pass_b": b, "pass_c": c}
+
+
+def timed(plan, psi, occ, kpsi, ex, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+    torch.cuda.synchronize()
+    plan.enable_profiling(True)
+    plan.read_profile()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    if torch.distributed.is_available() and torch.distributed.is_initialized():
+        torch.distributed.barrier()
+    torch.cuda.synchronize()
+    t_host = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_host
+    ms = e0.elapsed_time(e1) / steps
+    prof = plan.read_profile()
+    plan.enable_profiling(False)
+    return ms, wall, prof
+
+
+def cpu_baseline(sysm, n_sample: int) -> dict:
+    """The FP64 oracle as it stands, timed on a subset of the orbitals."""
+    workers = min(16, os.cpu_count() or 1)
+    os.environ["EXX_ORACLE_WORKERS"] = str(workers)
+    import oracle
+    psi = sysm.psi[:n_sample].copy()
+    occ = sysm.occ[:n_sample].copy()
+    pairs = n_sample * (n_sample + 1) // 2
+    t0 = time.perf_counter()
+    oracle.exx(psi, occ, sysm.h, sysm.bc, R=sysm.R, symmetric=True)
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pair-solves/s", "cores": workers, "kind": "oracle",
+            "sample": f"all {pairs} pairs of the first {n_sample} of {sysm.n_orb} orbitals "
+                      f"(E_x and K psi), scipy.fft FP64 with workers={workers}, {dt:.1f} s"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="free64_n32")
+    ap.add_argument("--baseline-steps", type=int, default=3)
+    ap.add_argument("--no-baselines", action="store_true", help="skip the FP64 GPU paths")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=12)
+    a = ap.parse_args(argv)
+
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported "
+              "(the exchange path here is single-device).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1712_07973_amd as exx
+    from exx_inputs import pair_count, system
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    sysm = system(a.workload)
+    N, n = sysm.n_orb, sysm.n
+    pairs = pair_count(N)
+    ncls = 2 if sysm.bc == "free" else 1
+    grid = exx.Grid(n=n, h=sysm.h, bc=sysm.bc, R=sysm.R if sysm.bc == "free" else None)
+    psi = torch.from_numpy(sysm.psi).to(dev)
+    occ = torch.from_numpy(sysm.occ).to(dev)
+    kpsi = torch.empty_like(psi)
+    ex = torch.empty((), dtype=torch.float64, device=dev)
+
+    plan = exx.Plan(grid, "fp32", n_orb_max=N)
+    plan.workspace(N)
+    _, n_slots = plan.schedule_info(N)
+    ms, wall, prof = timed(plan, psi, occ, kpsi, ex, a.steps, a.warmup)
+    value = pairs / (ms * 1e-3)
+    E32 = float(ex.item())
+    K32 = kpsi.clone()
+
+    # dominant kernel and its roofline
+    passes = {k: v for k, v in prof.items() if v[1] > 0}
+    dom = max(("pass_a", "pass_b", "pass_c"), key=lambda k: passes.get(k, (0, 0))[0])
+    dom_ms, dom_launches = passes[dom]
+    per_launch_ms = dom_ms / dom_launches
+    launches_per_step = dom_launches / a.steps
+    alg = algorithmic_bytes(n, ncls, N, n_slots)
+    flops = fft_flops(n, ncls, n_slots, share_y=(ncls == 2 and n <= 64))
+    bytes_per_launch = alg[dom] / launches_per_step
+    achieved_gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    achieved_tflops = flops[dom] / launches_per_step / (per_launch_ms * 1e-3) / 1e12
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "bytes_per_launch": int(bytes_per_launch), "launch_ms": round(per_launch_ms, 4),
+                "fft_tflops": round(achieved_tflops, 2),
+                "fft_frac_of_fp32_vector_peak": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
+    whole_alg = sum(alg.values())
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "pair-solves/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "free-BC 64^3 grid padded to 128^3, h=0.4 bohr, R=L=25.6 bohr, "
+                               "32 Loewdin-orthonormalised Gaussian orbitals, occupations 2, "
+                               "528 pair solves, E_x + K psi",
+                   "preset": a.workload, "n": n, "fft_grid": ncls * n, "n_orb": N,
+                   "pairs": pairs, "packed_slots": n_slots, "tuning": plan.tuning},
+        "roofline": roofline,
+        "whole_step_algorithmic_GBs": round(whole_alg / (ms * 1e-3) / 1e9, 1),
+        "passes_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in passes.items()},
+        "host_wall_ms_per_step": round(wall * 1e3 / a.steps, 4),
+        "E_x": E32,
+    }
+
+    if not a.no_baselines:
+        for prec in ("fp64_plain", "fp64_fused"):
+            p64 = exx.Plan(grid, prec, n_orb_max=N)
+            p64.workspace(N)
+            k64 = torch.empty_like(psi)
+            e64 = torch.empty((), dtype=torch.float64, device=dev)
+            ms64, _, _ = timed(p64, psi, occ, k64, e64, a.baseline_steps, 1)
+            out[prec] = {"value": round(pairs / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 3)}
+            if prec == "fp64_plain":
+                E64 = float(e64.item())
+                num = torch.linalg.vector_norm((K32 - k64).reshape(N, -1), dim=1)
+                den = torch.linalg.vector_norm(k64.reshape(N, -1), dim=1)
+                out["accuracy_vs_fp64_plain"] = {
+                    "dE_x_per_orbital_Ha": abs(E32 - E64) / N,
+                    "kpsi_max_rel_l2": float((num / den).max().item())}
+                out["speedup_vs_fp64_plain"] = round(value / out[prec]["value"], 2)
+            del p64, k64
+            torch.cuda.empty_cache()
+
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sysm, min(a.cpu_sample, N))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

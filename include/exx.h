@@ -171,6 +171,32 @@ int exx_batch_workspace_bytes(const exx_batch* batch, size_t* bytes);
 int exx_batch_compute(exx_batch* batch, const exx_system* systems, int mode, unsigned flags,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* ---- profiling ----------------------------------------------------------- */
+/* Per-pass device time measured with hipEvents recorded on the compute stream
+ * around every kernel launch of exx_compute (not while a graph is captured).
+ * Pass kinds index ms[] / launches[]: */
+enum exx_pass_kind {
+  EXX_PASS_CONVERT = 0, /* FP64 -> FP32 orbital copy */
+  EXX_PASS_ZERO = 1,    /* clearing accumulators */
+  EXX_PASS_A = 2,       /* co-densities + forward x-transform */
+  EXX_PASS_B = 3,       /* y/z transforms, kernel multiply, inverse y/z */
+  EXX_PASS_C = 4,       /* inverse x-transform, pair energies, K psi */
+  EXX_PASS_FINALIZE = 5,
+  EXX_PASS_PLAIN_FFT = 6,   /* plain path: one axis transform */
+  EXX_PASS_PLAIN_OTHER = 7, /* plain path: build, kernel multiply, reduce */
+  EXX_PASS_KINDS = 8
+};
+typedef struct exx_pass_times {
+  double ms[EXX_PASS_KINDS];
+  long long launches[EXX_PASS_KINDS];
+} exx_pass_times;
+
+/* Enables (1) or disables (0) event recording for later exx_compute calls. */
+int exx_plan_enable_profiling(exx_plan* plan, int enable);
+/* Waits for the recorded events, returns the accumulated times since the last
+ * read and resets them. */
+int exx_plan_read_profile(exx_plan* plan, exx_pass_times* out);
+
 /* ---- diagnostics --------------------------------------------------------- */
 const char* exx_error_string(int code);
 const char* exx_last_error(void);

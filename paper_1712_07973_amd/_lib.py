@@ -36,6 +36,14 @@ class ExxTuning(C.Structure):
                 ("zblock_c", C.c_int)]
 
 
+PASS_KINDS = ["convert", "zero", "pass_a", "pass_b", "pass_c", "finalize", "plain_fft",
+              "plain_other"]
+
+
+class ExxPassTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_longlong * 8)]
+
+
 class ExxSystem(C.Structure):
     _fields_ = [("psi", C.c_void_p), ("occ", C.c_void_p), ("ex_out", C.c_void_p),
                 ("kpsi", C.c_void_p), ("pair_e", C.c_void_p)]
@@ -64,6 +72,8 @@ SIGNATURES = {
     "exx_plan_schedule_info": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_longlong),
                                          C.POINTER(C.c_longlong)]),
     "exx_version": (C.c_char_p, []),
+    "exx_plan_enable_profiling": (C.c_int, [C.c_void_p, C.c_int]),
+    "exx_plan_read_profile": (C.c_int, [C.c_void_p, C.POINTER(ExxPassTimes)]),
 }
 
 _lib = None

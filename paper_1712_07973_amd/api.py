@@ -137,6 +137,16 @@ class Plan:
         t = L.ExxTuning(int(tile), int(batch_slots), int(zblock_a), int(zblock_c))
         L.check(L.lib().exx_plan_set_tuning(self._h, C.byref(t)), "exx_plan_set_tuning")
 
+    def enable_profiling(self, on: bool = True) -> None:
+        L.check(L.lib().exx_plan_enable_profiling(self._h, 1 if on else 0),
+                "exx_plan_enable_profiling")
+
+    def read_profile(self) -> dict:
+        """{pass kind: (total ms, launches)} since the last read (waits for the events)."""
+        t = L.ExxPassTimes()
+        L.check(L.lib().exx_plan_read_profile(self._h, C.byref(t)), "exx_plan_read_profile")
+        return {k: (t.ms[i], int(t.launches[i])) for i, k in enumerate(L.PASS_KINDS)}
+
     def compute(self, psi: torch.Tensor, occ: torch.Tensor, mode: str = "energy_kpsi",
                 kpsi: torch.Tensor | None = None, pair_e: torch.Tensor | None = None,
                 ex_out: torch.Tensor | None = None, accumulate: bool = False,

@@ -113,7 +113,7 @@ size_t slot_bytes(const exx_plan* p) {
 }
 
 void default_tuning(exx_plan* p) {
-  p->tuning.tile = 4;
+  p->tuning.tile = pass_c_max_tile(p->n);
   const size_t budget = (size_t)4 << 30;  // bytes of spectrum workspace per launch chunk
   size_t per = slot_bytes(p);
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
@@ -122,55 +122,8 @@ void default_tuning(exx_plan* p) {
 }
 
 void build_schedule(const exx_plan* p, int N, Schedule& s) {
-  s = Schedule();
-  s.n_orb = N;
-  s.n_pairs = (long long)N * (N + 1) / 2;
-  s.batch_slots = p->tuning.batch_slots;
-  if (is_plain(p)) {
-    s.tile = 0;
-    for (int i = 0; i < N; ++i)
-      for (int j = i; j < N; ++j) s.slots.push_back({i, j, -1, -1});
-    int cap = std::max(1, p->tuning.batch_slots);
-    for (int s0 = 0; s0 < (int)s.slots.size(); s0 += cap)
-      s.chunks.push_back({0, 0, s0, std::min<int>((int)s.slots.size(), s0 + cap)});
-    return;
-  }
-  const int T = std::max(1, std::min(p->tuning.tile, 4));
-  s.tile = T;
-  const int nt = (N + T - 1) / T;
-  for (int I = 0; I < nt; ++I)
-    for (int J = I; J < nt; ++J) {
-      TilePair tp{};
-      tp.I0 = I * T;
-      tp.nI = std::min(T, N - tp.I0);
-      tp.J0 = J * T;
-      tp.nJ = std::min(T, N - tp.J0);
-      tp.diag = (I == J);
-      std::vector<std::pair<int, int>> pairs;
-      for (int a = 0; a < tp.nI; ++a)
-        for (int b = tp.diag ? a : 0; b < tp.nJ; ++b) pairs.push_back({tp.I0 + a, tp.J0 + b});
-      tp.s0 = (int)s.slots.size();
-      for (size_t k = 0; k < pairs.size(); k += 2) {
-        Slot sl{pairs[k].first, pairs[k].second, -1, -1};
-        if (k + 1 < pairs.size()) {
-          sl.ib = pairs[k + 1].first;
-          sl.jb = pairs[k + 1].second;
-        }
-        s.slots.push_back(sl);
-      }
-      tp.s1 = (int)s.slots.size();
-      s.tiles.push_back(tp);
-    }
-  // chunks of whole tiles whose slots fit the launch capacity
-  const int cap = std::max(p->tuning.batch_slots, T * T);
-  int t0 = 0;
-  while (t0 < (int)s.tiles.size()) {
-    int t1 = t0;
-    while (t1 < (int)s.tiles.size() && s.tiles[t1].s1 - s.tiles[t0].s0 <= cap) ++t1;
-    if (t1 == t0) t1 = t0 + 1;
-    s.chunks.push_back({t0, t1, s.tiles[t0].s0, s.tiles[t1 - 1].s1});
-    t0 = t1;
-  }
+  const int T = is_plain(p) ? 0 : std::max(1, std::min(p->tuning.tile, pass_c_max_tile(p->n)));
+  build_schedule_host(N, T, p->tuning.batch_slots, !is_plain(p), s);
 }
 
 int cap_slots(const exx_plan* p, const Schedule& s) {
@@ -198,7 +151,8 @@ WsLayout layout(const exx_plan* p, const Schedule& s) {
 
 int get_schedule(exx_plan* p, int N, Schedule** out, bool allow_build) {
   auto it = p->schedules.find(N);
-  if (it != p->schedules.end() && it->second.tile == (is_plain(p) ? 0 : std::min(p->tuning.tile, 4)) &&
+  if (it != p->schedules.end() &&
+      it->second.tile == (is_plain(p) ? 0 : std::max(1, std::min(p->tuning.tile, pass_c_max_tile(p->n)))) &&
       it->second.batch_slots == p->tuning.batch_slots) {
     *out = &it->second;
     return EXX_OK;
@@ -228,6 +182,34 @@ int get_schedule(exx_plan* p, int N, Schedule** out, bool allow_build) {
 
 bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
 
+// Brackets one launch with a pair of events when profiling is on.
+struct Prof {
+  exx_plan* p;
+  hipStream_t st;
+  size_t idx = (size_t)-1;
+  Prof(exx_plan* p_, int kind, hipStream_t st_) : p(p_), st(st_) {
+    if (!p->profile || !p->recording) return;
+    if (p->ev_used == p->ev_start.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      p->ev_start.push_back(a);
+      p->ev_stop.push_back(b);
+      p->ev_kind.push_back(kind);
+    }
+    idx = p->ev_used++;
+    p->ev_kind[idx] = kind;
+    (void)hipEventRecord(p->ev_start[idx], st);
+  }
+  ~Prof() {
+    if (idx != (size_t)-1) (void)hipEventRecord(p->ev_stop[idx], st);
+  }
+};
+#define EXX_PROF(kind) Prof prof_##__LINE__(p, kind, st)
+
 template <typename T>
 int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* psi,
               const double* occ, int N, int mode, unsigned flags, double* ex_out, double* kpsi,
@@ -239,27 +221,46 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   const T* psiT;
   if constexpr (sizeof(T) == 4) {
     float* p32 = reinterpret_cast<float*>(ws + w.psi32);
-    EXX_HIP(launch_convert(psi, p32, (size_t)N * n3, st));
+    {
+      EXX_PROF(EXX_PASS_CONVERT);
+      EXX_HIP(launch_convert(psi, p32, (size_t)N * n3, st));
+    }
     psiT = p32;
   } else {
     psiT = psi;
   }
   double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
   void* X = ws + w.X;
-  if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
-  if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
+  {
+    EXX_PROF(EXX_PASS_ZERO);
+    if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
+    if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
+  }
   Launch L{p->n, p->ncls, p->m, p->h3, st};
   for (const auto& c : s.chunks) {
     const int ns = c.s1 - c.s0;
-    EXX_HIP(launch_pass_a<T>(L, psiT, X, s.d_slots, c.s0, ns, occ, parseval, p->tuning.zblock_a, p->tables));
-    EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_slot, c.s0, p->tables));
-    if (!parseval)
-      EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, c.t0, c.t1 - c.t0, c.s0, kpsi,
-                               e_slot, want_k, want_e, p->tuning.zblock_c, 4, p->tables));
+    {
+      EXX_PROF(EXX_PASS_A);
+      EXX_HIP(launch_pass_a<T>(L, psiT, X, s.d_slots, c.s0, ns, occ, parseval, p->tuning.zblock_a, p->tables));
+    }
+    {
+      EXX_PROF(EXX_PASS_B);
+      EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_slot, c.s0, p->tables));
+    }
+    if (!parseval) {
+      for (int g = c.seg0; g < c.seg1; ++g) {
+        const auto& sg = s.segments[g];
+        EXX_PROF(EXX_PASS_C);
+        EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0, c.s0,
+                                 kpsi, e_slot, want_k, want_e, p->tuning.zblock_c, s.tile, p->tables));
+      }
+    }
   }
-  if (want_e)
+  if (want_e) {
+    EXX_PROF(EXX_PASS_FINALIZE);
     EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, parseval,
                             (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
+  }
   return EXX_OK;
 }
 
@@ -271,20 +272,40 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   const size_t n3 = (size_t)p->n * p->n * p->n;
   double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
   void* Z = ws + w.X;
-  if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
-  if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
+  {
+    EXX_PROF(EXX_PASS_ZERO);
+    if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
+    if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
+  }
   for (const auto& c : s.chunks) {
     const int np = c.s1 - c.s0;
-    EXX_HIP(plain_build(psi, s.d_slots, c.s0, np, p->n, p->m, Z, st));
-    for (int a = 0; a < 3; ++a) EXX_HIP(plain_fft_axis(Z, np, p->m, a, -1, p->tables, st));
-    EXX_HIP(plain_kernel_mul(Z, np, p->m, p->tables, st));
-    for (int a = 0; a < 3; ++a) EXX_HIP(plain_fft_axis(Z, np, p->m, a, +1, p->tables, st));
-    EXX_HIP(plain_reduce(Z, psi, occ, s.d_slots, c.s0, np, p->n, p->m, p->h3, kpsi, e_slot, want_k,
-                         want_e, st));
+    {
+      EXX_PROF(EXX_PASS_PLAIN_OTHER);
+      EXX_HIP(plain_build(psi, s.d_slots, c.s0, np, p->n, p->m, Z, st));
+    }
+    for (int a = 0; a < 3; ++a) {
+      EXX_PROF(EXX_PASS_PLAIN_FFT);
+      EXX_HIP(plain_fft_axis(Z, np, p->m, a, -1, p->tables, st));
+    }
+    {
+      EXX_PROF(EXX_PASS_PLAIN_OTHER);
+      EXX_HIP(plain_kernel_mul(Z, np, p->m, p->tables, st));
+    }
+    for (int a = 0; a < 3; ++a) {
+      EXX_PROF(EXX_PASS_PLAIN_FFT);
+      EXX_HIP(plain_fft_axis(Z, np, p->m, a, +1, p->tables, st));
+    }
+    {
+      EXX_PROF(EXX_PASS_PLAIN_OTHER);
+      EXX_HIP(plain_reduce(Z, psi, occ, s.d_slots, c.s0, np, p->n, p->m, p->h3, kpsi, e_slot, want_k,
+                           want_e, st));
+    }
   }
-  if (want_e)
+  if (want_e) {
+    EXX_PROF(EXX_PASS_FINALIZE);
     EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, false,
                             (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
+  }
   return EXX_OK;
 }
 
@@ -381,6 +402,10 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
 
 void exx_plan_destroy(exx_plan* p) {
   if (!p) return;
+  for (size_t i = 0; i < p->ev_start.size(); ++i) {
+    (void)hipEventDestroy(p->ev_start[i]);
+    (void)hipEventDestroy(p->ev_stop[i]);
+  }
   void* ptrs[] = {p->tables.tw, p->tables.md, p->tables.ktab, p->tables.tw_m, p->tables.ktab_m};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -427,8 +452,8 @@ int exx_plan_get_tuning(const exx_plan* p, exx_tuning* out) {
 
 int exx_plan_set_tuning(exx_plan* p, const exx_tuning* t) {
   if (!p || !t) return fail(EXX_ERR_INVALID_ARG, "plan or tuning is NULL");
-  if (t->tile < 0 || t->tile > 4 || t->batch_slots < 0)
-    return fail(EXX_ERR_INVALID_ARG, "tile must be in 1..4 and batch_slots >= 0");
+  if (t->tile < 0 || t->tile > 16 || t->batch_slots < 0)
+    return fail(EXX_ERR_INVALID_ARG, "tile must be in 1..16 (clamped to the pass limit) and batch_slots >= 0");
   if (t->tile) p->tuning.tile = t->tile;
   if (t->batch_slots) p->tuning.batch_slots = t->batch_slots;
   if (t->zblock_a) p->tuning.zblock_a = t->zblock_a;
@@ -462,9 +487,35 @@ int exx_compute(exx_plan* p, const double* psi, const double* occ, int n_orb, in
     return fail(EXX_ERR_WORKSPACE, "workspace smaller than exx_workspace_bytes(): need " + std::to_string(w.total));
   if (!aligned(ws, 256)) return fail(EXX_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
   char* wsc = static_cast<char*>(ws);
+  p->recording = (cap == hipStreamCaptureStatusNone);
   if (is_plain(p)) return run_plain(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
   if (is_fp32(p)) return run_fused<float>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
   return run_fused<double>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+}
+
+int exx_plan_enable_profiling(exx_plan* p, int enable) {
+  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
+  p->profile = enable != 0;
+  return EXX_OK;
+}
+
+int exx_plan_read_profile(exx_plan* p, exx_pass_times* out) {
+  if (!p || !out) return fail(EXX_ERR_INVALID_ARG, "plan or out is NULL");
+  for (size_t i = 0; i < p->ev_used; ++i) {
+    EXX_HIP(hipEventSynchronize(p->ev_stop[i]));
+    float ms = 0.f;
+    EXX_HIP(hipEventElapsedTime(&ms, p->ev_start[i], p->ev_stop[i]));
+    p->prof_ms[p->ev_kind[i]] += ms;
+    p->prof_launches[p->ev_kind[i]] += 1;
+  }
+  p->ev_used = 0;
+  for (int k = 0; k < EXX_PASS_KINDS; ++k) {
+    out->ms[k] = p->prof_ms[k];
+    out->launches[k] = p->prof_launches[k];
+    p->prof_ms[k] = 0;
+    p->prof_launches[k] = 0;
+  }
+  return EXX_OK;
 }
 
 }  // extern "C"

@@ -180,7 +180,7 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   }
   exx_tuning base = p->tuning, best = base;
   float best_ms = 1e30f;
-  std::vector<int> tiles = {2, 4};
+  std::vector<int> tiles = {4, 8};
   std::vector<int> batches = {32, 64, 128, 256, 1 << 20};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EXX_ERR_HIP;

@@ -168,18 +168,193 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
 
 // ---------------------------------------------------------------------------
 // pass B: per (slot, cx, kx) slab [y][z]: 2-D forward transform per (cy, cz)
-// class, kernel multiply, 2-D inverse transform, demodulate and sum classes.
-// Energy-only variant: accumulate sum_k K |Z|^2 (Parseval) instead.
+// class, kernel multiply (Eq. 4 in Fourier space), 2-D inverse transform,
+// demodulation and sum over classes.  A z-modulation is constant along y, so
+// it commutes with the y-transform: with SHARE_Y the forward and inverse
+// y-transforms are done once per cy and shared by both z classes (the
+// y-transformed columns and the partial z sums then live in registers); for
+// large slabs whose registers would spill, each class is transformed
+// separately.  Energy-only variant: accumulate sum K |Z|^2 (Parseval).
 // LDS layouts: A = [y][z] (pitch N), B = [z][y] (pitch N+1), same storage.
+// Register arrays indexed by items (line, t), t < L2, holding L1 values:
+//   acc : output, items (z, t) holding y = t + L2 k1
+//   yv  : y-transformed columns, items (ky, t) holding z = t + L2 k1
+//   wacc: sum over cz of the z-convolved columns, items (ky, t)
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NCLS, int NT, bool EONLY>
+template <typename T, int N, int NT>
+struct SlabFft {
+  using S = Split<N>;
+  static constexpr int L1 = S::L1, L2 = S::L2;
+  static constexpr int PB = N + 1;
+  static constexpr int C1 = N * L2;  // items (line, t)
+  static constexpr int C2 = N * L1;  // items (line, q1)
+  static constexpr int I1 = (C1 + NT - 1) / NT;
+  static constexpr int I2 = (C2 + NT - 1) / NT;
+  static __device__ __forceinline__ bool ok1(int it) { return C1 % NT == 0 || it < C1; }
+  static __device__ __forceinline__ bool ok2(int it) { return C2 % NT == 0 || it < C2; }
+
+  // y forward step 1 from the global slab (modulated by md^(cy y + cz z)) -> layout A
+  static __device__ __forceinline__ void y_fwd1(const cpx<T>* g, cpx<T>* lds, const cpx<T>* tw,
+                                                const cpx<T>* md, int cy, int cz, int tid) {
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (ok1(it)) {
+        int z = it % N, t = it / N;
+        cpx<T> v[L1];
+        cpx<T> mz = cz ? md[z] : cpx<T>{T(1), T(0)};
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) {
+          cpx<T> a = g[(t + L2 * k1) * N + z];
+          if (cy) a = cmul(a, md[t + L2 * k1]);
+          if (cz) a = cmul(a, mz);
+          v[k1] = a;
+        }
+        Dft<L1, -1, T>::run(v);
+#pragma unroll
+        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * N + z] = v[q1];
+      }
+    }
+  }
+  // y forward step 2: layout A -> layout B (ky in natural order)
+  static __device__ __forceinline__ void y_fwd2(cpx<T>* lds, int tid) {
+    cpx<T> w[I2][L2];
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (ok2(it)) {
+        int z = it % N, q1 = it / N;
+#pragma unroll
+        for (int t = 0; t < L2; ++t) w[ii][t] = lds[(t + L2 * q1) * N + z];
+        Dft<L2, -1, T>::run(w[ii]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (ok2(it)) {
+        int z = it % N, q1 = it / N;
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) lds[z * PB + q1 + L1 * q2] = w[ii][q2];
+      }
+    }
+  }
+  // z forward step 1 on one item: values v (z = t + L2 k1) -> layout B in place
+  static __device__ __forceinline__ void z_fwd1_item(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw,
+                                                     int ky, int t) {
+    Dft<L1, -1, T>::run(v);
+#pragma unroll
+    for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+    for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * PB + ky] = v[q1];
+  }
+  // z forward step 2, kernel multiply (or Parseval sum), inverse step 2, in place
+  template <bool EONLY, int M>
+  static __device__ __forceinline__ void z_mid(cpx<T>* lds, const cpx<T>* tw, const T* kt,
+                                               int cy, int cz, double& esum, int tid) {
+    constexpr int H = M / 2 + 1;
+    constexpr bool PAD = (M == 2 * N);
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (ok2(it)) {
+        int ky = it % N, q1 = it / N;
+        cpx<T> v[L2];
+#pragma unroll
+        for (int t = 0; t < L2; ++t) v[t] = lds[(t + L2 * q1) * PB + ky];
+        Dft<L2, -1, T>::run(v);
+        const int kyf = PAD ? 2 * ky + cy : ky;
+        const T* kr = kt + (size_t)fold(kyf, M) * H;
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) {
+          int kz = q1 + L1 * q2;
+          int kzf = PAD ? 2 * kz + cz : kz;
+          T kv = kr[fold(kzf, M)];
+          if (EONLY) {
+            esum += (double)kv *
+                    ((double)v[q2].x * (double)v[q2].x + (double)v[q2].y * (double)v[q2].y);
+          } else {
+            v[q2].x *= kv;
+            v[q2].y *= kv;
+          }
+        }
+        if (!EONLY) {
+          Dft<L2, 1, T>::run(v);
+#pragma unroll
+          for (int t = 1; t < L2; ++t) v[t] = cmulc(v[t], tw[t * q1]);
+#pragma unroll
+          for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * PB + ky] = v[t];
+        }
+      }
+    }
+  }
+  // z inverse step 1 on one item: layout B -> values v (z = t + L2 k1)
+  static __device__ __forceinline__ void z_inv1_item(cpx<T>* v, const cpx<T>* lds, int ky, int t) {
+#pragma unroll
+    for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * PB + ky];
+    Dft<L1, 1, T>::run(v);
+  }
+  // y inverse step 2: layout B -> layout A
+  static __device__ __forceinline__ void y_inv2(cpx<T>* lds, const cpx<T>* tw, int tid) {
+    cpx<T> w[I2][L2];
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (ok2(it)) {
+        int z = it % N, q1 = it / N;
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = lds[z * PB + q1 + L1 * q2];
+        Dft<L2, 1, T>::run(w[ii]);
+#pragma unroll
+        for (int t = 1; t < L2; ++t) w[ii][t] = cmulc(w[ii][t], tw[t * q1]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < I2; ++ii) {
+      int it = tid + ii * NT;
+      if (ok2(it)) {
+        int z = it % N, q1 = it / N;
+#pragma unroll
+        for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * N + z] = w[ii][t];
+      }
+    }
+  }
+  // y inverse step 1, demodulate (cy, cz) and accumulate into acc
+  static __device__ __forceinline__ void y_inv1(const cpx<T>* lds, const cpx<T>* md, int cy, int cz,
+                                                cpx<T> (&acc)[I1][L1], int tid) {
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (ok1(it)) {
+        int z = it % N, t = it / N;
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * N + z];
+        Dft<L1, 1, T>::run(v);
+        cpx<T> mz = cz ? md[z] : cpx<T>{T(1), T(0)};
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) {
+          cpx<T> a = v[k1];
+          if (cy) a = cmulc(a, md[t + L2 * k1]);
+          if (cz) a = cmulc(a, mz);
+          acc[ii][k1] = cadd(acc[ii][k1], a);
+        }
+      }
+    }
+  }
+};
+
+template <typename T, int N, int NCLS, int NT, bool EONLY, bool SHARE_Y>
 __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* __restrict__ ktab,
                                                const cpx<T>* __restrict__ twg,
                                                const cpx<T>* __restrict__ mdg,
                                                double* __restrict__ e_slot, int slot0) {
-  using S = Split<N>;
-  constexpr int L1 = S::L1, L2 = S::L2;
-  constexpr int PB = N + 1;
+  using F = SlabFft<T, N, NT>;
+  constexpr int L1 = F::L1, L2 = F::L2, PB = F::PB, I1 = F::I1;
   constexpr int M = NCLS * N;
   constexpr int H = M / 2 + 1;
   __shared__ cpx<T> lds[N * PB];
@@ -198,197 +373,125 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
   }
-
-  constexpr int C1 = N * L2;  // items (line, t)
-  constexpr int C2 = N * L1;  // items (line, q1)
-  constexpr int I1 = (C1 + NT - 1) / NT;
-  constexpr int I2 = (C2 + NT - 1) / NT;
-
-  cpx<T> xin[I1][L1];
   cpx<T> acc[I1][L1];
 #pragma unroll
-  for (int ii = 0; ii < I1; ++ii) {
-    int it = tid + ii * NT;
-    if (C1 % NT == 0 || it < C1) {
-      int z = it % N, t = it / N;
+  for (int ii = 0; ii < I1; ++ii)
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) {
-        xin[ii][k1] = g[(t + L2 * k1) * N + z];
-        acc[ii][k1] = {T(0), T(0)};
-      }
-    }
-  }
+    for (int k1 = 0; k1 < L1; ++k1) acc[ii][k1] = {T(0), T(0)};
   double esum = 0.0;
   __syncthreads();
 
+  if constexpr (SHARE_Y) {
 #pragma unroll 1
-  for (int cls = 0; cls < NCLS * NCLS; ++cls) {
-    const int cy = NCLS == 2 ? (cls >> 1) : 0;
-    const int cz = NCLS == 2 ? (cls & 1) : 0;
-    // step 1: y forward, items (z, t): reads input, writes layout A
-#pragma unroll
-    for (int ii = 0; ii < I1; ++ii) {
-      int it = tid + ii * NT;
-      if (C1 % NT == 0 || it < C1) {
-        int z = it % N, t = it / N;
-        cpx<T> v[L1];
-        cpx<T> mz = (NCLS == 2 && cz) ? md[z] : cpx<T>{T(1), T(0)};
-#pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) {
-          cpx<T> a = xin[ii][k1];
-          if (NCLS == 2 && cy) a = cmul(a, md[t + L2 * k1]);
-          if (NCLS == 2 && cz) a = cmul(a, mz);
-          v[k1] = a;
-        }
-        Dft<L1, -1, T>::run(v);
-#pragma unroll
-        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
-#pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * N + z] = v[q1];
-      }
-    }
-    __syncthreads();
-    // step 2: y forward, items (z, q1): layout A -> layout B (ky natural order)
-    {
-      cpx<T> w[I2][L2];
-#pragma unroll
-      for (int ii = 0; ii < I2; ++ii) {
-        int it = tid + ii * NT;
-        if (C2 % NT == 0 || it < C2) {
-          int z = it % N, q1 = it / N;
-#pragma unroll
-          for (int t = 0; t < L2; ++t) w[ii][t] = lds[(t + L2 * q1) * N + z];
-          Dft<L2, -1, T>::run(w[ii]);
-        }
-      }
+    for (int cy = 0; cy < NCLS; ++cy) {
+      F::y_fwd1(g, lds, tw, md, cy, 0, tid);
       __syncthreads();
+      F::y_fwd2(lds, tid);
+      __syncthreads();
+      cpx<T> yv[I1][L1];
+      cpx<T> wacc[I1][L1];
 #pragma unroll
-      for (int ii = 0; ii < I2; ++ii) {
+      for (int ii = 0; ii < I1; ++ii) {
         int it = tid + ii * NT;
-        if (C2 % NT == 0 || it < C2) {
-          int z = it % N, q1 = it / N;
+        if (F::ok1(it)) {
+          int ky = it % N, t = it / N;
 #pragma unroll
-          for (int q2 = 0; q2 < L2; ++q2) lds[z * PB + q1 + L1 * q2] = w[ii][q2];
-        }
-      }
-    }
-    __syncthreads();
-    // step 3: z forward step 1, items (ky, t), in place in layout B
-#pragma unroll
-    for (int ii = 0; ii < I1; ++ii) {
-      int it = tid + ii * NT;
-      if (C1 % NT == 0 || it < C1) {
-        int ky = it % N, t = it / N;
-        cpx<T> v[L1];
-#pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) v[k1] = lds[(t + L2 * k1) * PB + ky];
-        Dft<L1, -1, T>::run(v);
-#pragma unroll
-        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
-#pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * PB + ky] = v[q1];
-      }
-    }
-    __syncthreads();
-    // step 4: z forward step 2 -> spectrum, kernel multiply, inverse step 2
-#pragma unroll
-    for (int ii = 0; ii < I2; ++ii) {
-      int it = tid + ii * NT;
-      if (C2 % NT == 0 || it < C2) {
-        int ky = it % N, q1 = it / N;
-        cpx<T> v[L2];
-#pragma unroll
-        for (int t = 0; t < L2; ++t) v[t] = lds[(t + L2 * q1) * PB + ky];
-        Dft<L2, -1, T>::run(v);
-        const int kyf = NCLS == 2 ? 2 * ky + cy : ky;
-        const T* kr = kt + (size_t)fold(kyf, M) * H;
-#pragma unroll
-        for (int q2 = 0; q2 < L2; ++q2) {
-          int kz = q1 + L1 * q2;
-          int kzf = NCLS == 2 ? 2 * kz + cz : kz;
-          T kv = kr[fold(kzf, M)];
-          if (EONLY) {
-            esum += (double)kv * ((double)v[q2].x * (double)v[q2].x +
-                                  (double)v[q2].y * (double)v[q2].y);
-          } else {
-            v[q2].x *= kv;
-            v[q2].y *= kv;
+          for (int k1 = 0; k1 < L1; ++k1) {
+            yv[ii][k1] = lds[(t + L2 * k1) * PB + ky];
+            wacc[ii][k1] = {T(0), T(0)};
           }
         }
-        if (!EONLY) {
-          Dft<L2, 1, T>::run(v);
+      }
+      __syncthreads();
+#pragma unroll 1
+      for (int cz = 0; cz < NCLS; ++cz) {
 #pragma unroll
-          for (int t = 1; t < L2; ++t) v[t] = cmulc(v[t], tw[t * q1]);
+        for (int ii = 0; ii < I1; ++ii) {
+          int it = tid + ii * NT;
+          if (F::ok1(it)) {
+            int ky = it % N, t = it / N;
+            cpx<T> v[L1];
 #pragma unroll
-          for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * PB + ky] = v[t];
+            for (int k1 = 0; k1 < L1; ++k1)
+              v[k1] = cz ? cmul(yv[ii][k1], md[t + L2 * k1]) : yv[ii][k1];
+            F::z_fwd1_item(v, lds, tw, ky, t);
+          }
         }
+        __syncthreads();
+        F::template z_mid<EONLY, M>(lds, tw, kt, cy, cz, esum, tid);
+        __syncthreads();
+        if (EONLY) continue;
+#pragma unroll
+        for (int ii = 0; ii < I1; ++ii) {
+          int it = tid + ii * NT;
+          if (F::ok1(it)) {
+            int ky = it % N, t = it / N;
+            cpx<T> v[L1];
+            F::z_inv1_item(v, lds, ky, t);
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1)
+              wacc[ii][k1] = cadd(wacc[ii][k1], cz ? cmulc(v[k1], md[t + L2 * k1]) : v[k1]);
+          }
+        }
+        __syncthreads();
       }
-    }
-    __syncthreads();
-    if (EONLY) continue;
-    // step 5: z inverse step 1, items (ky, t), in place
+      if (EONLY) continue;
 #pragma unroll
-    for (int ii = 0; ii < I1; ++ii) {
-      int it = tid + ii * NT;
-      if (C1 % NT == 0 || it < C1) {
-        int ky = it % N, t = it / N;
-        cpx<T> v[L1];
-#pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * PB + ky];
-        Dft<L1, 1, T>::run(v);
-#pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) lds[(t + L2 * k1) * PB + ky] = v[k1];
-      }
-    }
-    __syncthreads();
-    // step 6: y inverse step 2, items (z, q1): layout B -> layout A
-    {
-      cpx<T> w[I2][L2];
-#pragma unroll
-      for (int ii = 0; ii < I2; ++ii) {
+      for (int ii = 0; ii < I1; ++ii) {
         int it = tid + ii * NT;
-        if (C2 % NT == 0 || it < C2) {
-          int z = it % N, q1 = it / N;
+        if (F::ok1(it)) {
+          int ky = it % N, t = it / N;
 #pragma unroll
-          for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = lds[z * PB + q1 + L1 * q2];
-          Dft<L2, 1, T>::run(w[ii]);
-#pragma unroll
-          for (int t = 1; t < L2; ++t) w[ii][t] = cmulc(w[ii][t], tw[t * q1]);
+          for (int k1 = 0; k1 < L1; ++k1) lds[(t + L2 * k1) * PB + ky] = wacc[ii][k1];
         }
       }
       __syncthreads();
+      F::y_inv2(lds, tw, tid);
+      __syncthreads();
+      F::y_inv1(lds, md, cy, 0, acc, tid);
+      __syncthreads();
+    }
+  } else {
+#pragma unroll 1
+    for (int cls = 0; cls < NCLS * NCLS; ++cls) {
+      const int cy = NCLS == 2 ? (cls >> 1) : 0;
+      const int cz = NCLS == 2 ? (cls & 1) : 0;
+      F::y_fwd1(g, lds, tw, md, cy, cz, tid);
+      __syncthreads();
+      F::y_fwd2(lds, tid);
+      __syncthreads();
 #pragma unroll
-      for (int ii = 0; ii < I2; ++ii) {
+      for (int ii = 0; ii < I1; ++ii) {
         int it = tid + ii * NT;
-        if (C2 % NT == 0 || it < C2) {
-          int z = it % N, q1 = it / N;
+        if (F::ok1(it)) {
+          int ky = it % N, t = it / N;
+          cpx<T> v[L1];
 #pragma unroll
-          for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * N + z] = w[ii][t];
+          for (int k1 = 0; k1 < L1; ++k1) v[k1] = lds[(t + L2 * k1) * PB + ky];
+          F::z_fwd1_item(v, lds, tw, ky, t);
         }
       }
-    }
-    __syncthreads();
-    // step 7: y inverse step 1, items (z, t): demodulate and accumulate
+      __syncthreads();
+      F::template z_mid<EONLY, M>(lds, tw, kt, cy, cz, esum, tid);
+      __syncthreads();
+      if (EONLY) continue;
 #pragma unroll
-    for (int ii = 0; ii < I1; ++ii) {
-      int it = tid + ii * NT;
-      if (C1 % NT == 0 || it < C1) {
-        int z = it % N, t = it / N;
-        cpx<T> v[L1];
+      for (int ii = 0; ii < I1; ++ii) {
+        int it = tid + ii * NT;
+        if (F::ok1(it)) {
+          int ky = it % N, t = it / N;
+          cpx<T> v[L1];
+          F::z_inv1_item(v, lds, ky, t);
 #pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * N + z];
-        Dft<L1, 1, T>::run(v);
-        cpx<T> mz = (NCLS == 2 && cz) ? md[z] : cpx<T>{T(1), T(0)};
-#pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) {
-          cpx<T> a = v[k1];
-          if (NCLS == 2 && cy) a = cmulc(a, md[t + L2 * k1]);
-          if (NCLS == 2 && cz) a = cmulc(a, mz);
-          acc[ii][k1] = cadd(acc[ii][k1], a);
+          for (int k1 = 0; k1 < L1; ++k1) lds[(t + L2 * k1) * PB + ky] = v[k1];
         }
       }
+      __syncthreads();
+      F::y_inv2(lds, tw, tid);
+      __syncthreads();
+      F::y_inv1(lds, md, cy, cz, acc, tid);
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   if (EONLY) {
@@ -400,31 +503,55 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
     if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
     if (tid == 0) {
-      double s = 0.0;
-      for (int w = 0; w < NT / 64; ++w) s += red[w];
-      atomicAdd(&e_slot[2 * (slot0 + ls)], s);
+      double sum = 0.0;
+      for (int w = 0; w < NT / 64; ++w) sum += red[w];
+      atomicAdd(&e_slot[2 * (slot0 + ls)], sum);
     }
     return;
-  }
+  } else {
+    // every block has read its whole slab (first class) before any write here
 #pragma unroll
-  for (int ii = 0; ii < I1; ++ii) {
-    int it = tid + ii * NT;
-    if (C1 % NT == 0 || it < C1) {
-      int z = it % N, t = it / N;
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (F::ok1(it)) {
+        int z = it % N, t = it / N;
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) g[(t + L2 * k1) * N + z] = acc[ii][k1];
+        for (int k1 = 0; k1 < L1; ++k1) g[(t + L2 * k1) * N + z] = acc[ii][k1];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// pass C: inverse x-transform of every slot of a pair tile for rows
-// (y, z0..z0+ZB), then FP64 pair energies and K psi accumulation.
-// Each thread owns fixed grid points; the tile's orbitals are staged in LDS
-// (FP32/FP64 copies of psi) and the K psi partial sums kept in LDS in FP64,
-// flushed once per tile with FP64 atomics.
+// pass C: inverse x-transform of every slot of a pair tile for the rows
+// (y, z0..z0+ZB), then FP64 pair energies h^3 sum rho V (Eq. 5) and the
+// K psi sums (Eq. 3) of the tile's orbitals at the rows' points.
+//
+// Each thread owns L1 fixed grid points (x = t + 16 k1 of one row) and keeps
+// the K psi partial sums of every tile orbital at them in FP64 registers.
+// The tile pairs of one launch share no orbital (round-robin schedule), so
+// the final update of K psi is a plain read-modify-write: no atomics, and the
+// result does not depend on scheduling.  The next slot's spectrum rows are
+// prefetched into registers while the current slot is reduced.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NCLS, int ZB, int NT, int TMAX>
+template <int N>
+constexpr int pass_c_tile() {  // K psi register budget: 2*tile*L1 FP64 values per thread
+  return N / 16 <= 4 ? 8 : 4;
+}
+
+template <int NO, int L1>
+__device__ __forceinline__ void acc_add(double (&acc)[NO][L1], int lo, const double (&v)[L1]) {
+  // lo is uniform across the block, so this is a chain of scalar branches
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    if (k == lo) {
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) acc[k][k1] += v[k1];
+    }
+  }
+}
+
+template <typename T, int N, int NCLS, int ZB, int NT, int TM>
 __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
                                                const T* __restrict__ psi,
                                                const double* __restrict__ occ,
@@ -438,55 +565,61 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
   constexpr int NL = NCLS * ZB;
-  constexpr int NP = ZB * N;       // points per block
-  constexpr int NI = ZB * L2;      // point-owner items (zi, t), zi fastest
-  constexpr int NO = 2 * TMAX;     // orbitals per tile (I then J)
-  static_assert(NI == NT, "one point-owner item per thread");
+  constexpr int NO = 2 * TM;                 // orbitals per tile pair (I then J)
+  constexpr int NW = NT / 64;
+  constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched values per thread
+  static_assert(ZB * L2 == NT, "one point-owner item per thread");
   __shared__ cpx<T> xs[NL * P];
-  __shared__ T ps[NO * NP];
-  __shared__ double acc[NO * NP];
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
+  __shared__ double ered[NW][2];
 
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
   const int z0 = (blockIdx.x % (N / ZB)) * ZB;
   const TilePair tp = tiles[t0 + blockIdx.y];
   const size_t M3 = (size_t)N * N * N;
-  const int nloc = tp.diag ? tp.nI : TMAX + tp.nJ;
+  const int t_own = tid % L2, zi_own = tid / L2;
+  const size_t row = ((size_t)(z0 + zi_own) * N + y) * N;  // offset of the owned row
 
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
   }
-  // point index of (zi, t, k1): pt = k1 * NI + t * ZB + zi; x = t + L2 k1
-  // stage psi of the tile's orbitals (coalesced along x) and clear acc
-  for (int lo = 0; lo < nloc; ++lo) {
-    if (!tp.diag && lo >= tp.nI && lo < TMAX) continue;
-    int o = lo < TMAX ? tp.I0 + lo : tp.J0 + (lo - TMAX);
-    const T* po = psi + (size_t)o * M3;
-    for (int p = tid; p < NP; p += NT) {
-      int x = p % N, zi = p / N;
-      int t = x % L2, k1 = x / L2;
-      int pt = k1 * NI + t * ZB + zi;
-      ps[lo * NP + pt] = po[((size_t)(z0 + zi) * N + y) * N + x];
-      acc[lo * NP + pt] = 0.0;
-    }
-  }
-  __syncthreads();
+  double acc[NO][L1];
+#pragma unroll
+  for (int lo = 0; lo < NO; ++lo)
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) acc[lo][k1] = 0.0;
 
-  const int zi_own = tid % ZB, t_own = tid / ZB;
+  // spectrum rows of a slot: values p = tid + k NT -> (cx, kx, zi), zi fastest
+  cpx<T> pf[PF];
+  auto fetch = [&](int s) {
+    const cpx<T>* Xs = X + (size_t)(s - slot_base) * NCLS * M3;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      int p = tid + k * NT;
+      if ((NL * N) % NT == 0 || p < NL * N) {
+        int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
+        pf[k] = Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi];
+      }
+    }
+  };
+  if (tp.s0 < tp.s1) fetch(tp.s0);
 
 #pragma unroll 1
   for (int s = tp.s0; s < tp.s1; ++s) {
-    const Slot sl = slots[s];
-    const cpx<T>* Xs = X + (size_t)(s - slot_base) * NCLS * M3;
-    for (int p = tid; p < NCLS * N * ZB; p += NT) {
-      int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
-      xs[(cx * ZB + zi) * P + kx] = Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      int p = tid + k * NT;
+      if ((NL * N) % NT == 0 || p < NL * N) {
+        int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
+        xs[(cx * ZB + zi) * P + kx] = pf[k];
+      }
     }
+    if (s + 1 < tp.s1) fetch(s + 1);
     __syncthreads();
-    // inverse step 2 (per q1): IDFT_L2 over q2, conj twiddle
+    // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle
     constexpr int C2 = NL * L1;
     constexpr int I2 = (C2 + NT - 1) / NT;
     cpx<T> w[I2][L2];
@@ -513,7 +646,7 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
       }
     }
     __syncthreads();
-    // inverse step 1 (per t) for both x classes, demodulate: V_a + i V_b
+    // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b
     cpx<T> V[L1];
     {
       cpx<T> v[L1];
@@ -530,32 +663,48 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
         for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
       }
     }
-    // reductions at the owned points
-    const bool hb = sl.ib >= 0;
-    // local orbital slot: I block first; J block at TMAX (I and J disjoint off the diagonal)
-    auto loc = [&](int o) { return (o >= tp.I0 && o < tp.I0 + tp.nI) ? o - tp.I0 : TMAX + (o - tp.J0); };
-    const int la_i = loc(sl.ia), la_j = loc(sl.ja);
-    const int lb_i = hb ? loc(sl.ib) : 0, lb_j = hb ? loc(sl.jb) : 0;
-    const double fa_i = occ[sl.ia], fa_j = occ[sl.ja];
-    const double fb_i = hb ? occ[sl.ib] : 0.0, fb_j = hb ? occ[sl.jb] : 0.0;
+    // reductions at the owned points; slot data are uniform (scalar registers)
+    const int ia = __builtin_amdgcn_readfirstlane(slots[s].ia);
+    const int ja = __builtin_amdgcn_readfirstlane(slots[s].ja);
+    const int ib = __builtin_amdgcn_readfirstlane(slots[s].ib);
+    const int jb = __builtin_amdgcn_readfirstlane(slots[s].jb);
+    const bool hb = ib >= 0;
+    auto loc = [&](int o) { return (o >= tp.I0 && o < tp.I0 + tp.nI) ? o - tp.I0 : TM + (o - tp.J0); };
     double ea = 0.0, eb = 0.0;
+    {
+      const T* pi = psi + (size_t)ia * M3 + row;
+      const T* pj = psi + (size_t)ja * M3 + row;
+      double vi[L1], vj[L1];
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) {
-      const int pt = k1 * NI + tid;
-      const double Va = (double)V[k1].x, Vb = (double)V[k1].y;
-      const T pai = ps[la_i * NP + pt], paj = ps[la_j * NP + pt];
-      ea += (double)(pai * paj) * Va;
-      if (want_k) {
-        acc[la_i * NP + pt] += fa_j * Va * (double)paj;
-        if (sl.ia != sl.ja) acc[la_j * NP + pt] += fa_i * Va * (double)pai;
+      for (int k1 = 0; k1 < L1; ++k1) {
+        const int x = t_own + L2 * k1;
+        const T a = pi[x], b = pj[x];
+        const double Va = (double)V[k1].x;
+        ea += (double)(a * b) * Va;
+        vi[k1] = occ[ja] * Va * (double)b;  // into (K psi)_ia
+        vj[k1] = occ[ia] * Va * (double)a;  // into (K psi)_ja
       }
-      if (hb) {
-        const T pbi = ps[lb_i * NP + pt], pbj = ps[lb_j * NP + pt];
-        eb += (double)(pbi * pbj) * Vb;
-        if (want_k) {
-          acc[lb_i * NP + pt] += fb_j * Vb * (double)pbj;
-          if (sl.ib != sl.jb) acc[lb_j * NP + pt] += fb_i * Vb * (double)pbi;
-        }
+      if (want_k) {
+        acc_add<NO, L1>(acc, loc(ia), vi);
+        if (ia != ja) acc_add<NO, L1>(acc, loc(ja), vj);
+      }
+    }
+    if (hb) {
+      const T* pi = psi + (size_t)ib * M3 + row;
+      const T* pj = psi + (size_t)jb * M3 + row;
+      double vi[L1], vj[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        const int x = t_own + L2 * k1;
+        const T a = pi[x], b = pj[x];
+        const double Vb = (double)V[k1].y;
+        eb += (double)(a * b) * Vb;
+        vi[k1] = occ[jb] * Vb * (double)b;
+        vj[k1] = occ[ib] * Vb * (double)a;
+      }
+      if (want_k) {
+        acc_add<NO, L1>(acc, loc(ib), vi);
+        if (ib != jb) acc_add<NO, L1>(acc, loc(jb), vj);
       }
     }
     if (want_e) {
@@ -565,25 +714,29 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
         eb += __shfl_xor(eb, off);
       }
       if ((tid & 63) == 0) {
-        atomicAdd(&e_slot[2 * s], ea);
-        if (hb) atomicAdd(&e_slot[2 * s + 1], eb);
+        ered[tid >> 6][0] = ea;
+        ered[tid >> 6][1] = eb;
       }
     }
     __syncthreads();
+    if (want_e && tid < 2) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) sum += ered[w2][tid];
+      if (tid == 0 || hb) atomicAdd(&e_slot[2 * s + tid], sum);
+    }
   }
 
   if (!want_k) return;
-  // flush: coalesced FP64 atomics along x
-  for (int lo = 0; lo < nloc; ++lo) {
-    if (!tp.diag && lo >= tp.nI && lo < TMAX) continue;
-    int o = lo < TMAX ? tp.I0 + lo : tp.J0 + (lo - TMAX);
-    double* ko = kpsi + (size_t)o * M3;
-    for (int p = tid; p < NP; p += NT) {
-      int x = p % N, zi = p / N;
-      int t = x % L2, k1 = x / L2;
-      int pt = k1 * NI + t * ZB + zi;
-      atomicAdd(&ko[((size_t)(z0 + zi) * N + y) * N + x], acc[lo * NP + pt]);
-    }
+  // K psi += partial sums; the launch's tile pairs are orbital-disjoint
+#pragma unroll
+  for (int lo = 0; lo < NO; ++lo) {
+    const bool live = lo < TM ? (lo < tp.nI) : (!tp.diag && lo - TM < tp.nJ);
+    if (!live) continue;
+    const int o = lo < TM ? tp.I0 + lo : tp.J0 + (lo - TM);
+    double* ko = kpsi + (size_t)o * M3 + row;
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += acc[lo][k1];
   }
 }
 
@@ -661,8 +814,9 @@ bool fused_supported(int precision, int n) {
 
 template <typename T, int N>
 constexpr int pass_b_threads() {
-  // enough threads for a few items each; LDS bounds one block per CU at large N
-  return N <= 32 ? 128 : (N <= 64 ? 256 : 512);
+  // a few items per thread; from N = 96 on LDS allows one block per CU, so
+  // the block takes the whole CU (16 waves) to keep per-thread arrays small
+  return N <= 32 ? 128 : (N <= 64 ? 256 : ((N <= 80 || sizeof(T) == 8) ? 512 : 1024));
 }
 
 template <typename T>
@@ -696,6 +850,13 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
   });
 }
 
+template <typename T, int N>
+constexpr bool pass_b_share_y() {
+  // sharing the y-transforms keeps two more slab-sized register arrays live;
+  // only where that does not spill
+  return sizeof(T) == 4 ? N <= 64 : N <= 32;
+}
+
 template <typename T>
 hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
                          int slot0, const Tables& tb) {
@@ -705,6 +866,7 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
       return hipErrorInvalidValue;
     } else {
       constexpr int NT = pass_b_threads<T, N>();
+      constexpr bool SY = pass_b_share_y<T, N>();
       auto* Xc = static_cast<cpx<T>*>(X);
       auto* kt = static_cast<const T*>(tb.ktab);
       auto* tw = static_cast<const cpx<T>*>(tb.tw);
@@ -712,23 +874,36 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
       if (L.ncls == 2) {
         dim3 grid(2 * N, nslots);
         if (energy_only)
-          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, true>), grid, dim3(NT), 0, L.stream, Xc, kt,
-                             tw, md, e_slot, slot0);
+          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, true, SY>), grid, dim3(NT), 0, L.stream, Xc,
+                             kt, tw, md, e_slot, slot0);
         else
-          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, false>), grid, dim3(NT), 0, L.stream, Xc,
+          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, false, SY>), grid, dim3(NT), 0, L.stream, Xc,
                              kt, tw, md, e_slot, slot0);
       } else {
         dim3 grid(N, nslots);
         if (energy_only)
-          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, true>), grid, dim3(NT), 0, L.stream, Xc, kt,
-                             tw, md, e_slot, slot0);
+          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, true, false>), grid, dim3(NT), 0, L.stream,
+                             Xc, kt, tw, md, e_slot, slot0);
         else
-          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, false>), grid, dim3(NT), 0, L.stream, Xc,
-                             kt, tw, md, e_slot, slot0);
+          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, false, false>), grid, dim3(NT), 0, L.stream,
+                             Xc, kt, tw, md, e_slot, slot0);
       }
       return hipGetLastError();
     }
   });
+}
+
+int pass_c_max_tile(int n) {
+  switch (n) {
+    case 16: return pass_c_tile<16>();
+    case 32: return pass_c_tile<32>();
+    case 48: return pass_c_tile<48>();
+    case 64: return pass_c_tile<64>();
+    case 80: return pass_c_tile<80>();
+    case 96: return pass_c_tile<96>();
+    case 112: return pass_c_tile<112>();
+    default: return pass_c_tile<128>();
+  }
 }
 
 template <typename T>
@@ -742,22 +917,23 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
     if constexpr (sizeof(T) == 8 && N > 96) {
       return hipErrorInvalidValue;
     } else {
-    constexpr int ZB = 8;
-    constexpr int NT = ZB * 16;
-    dim3 grid(N * (N / ZB), ntiles);
-    auto* Xc = static_cast<const cpx<T>*>(X);
-    auto* tw = static_cast<const cpx<T>*>(tb.tw);
-    auto* md = static_cast<const cpx<T>*>(tb.md);
-    if (tmax > 4) return hipErrorInvalidValue;
-    if (L.ncls == 2)
-      hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, 4>), grid, dim3(NT), 0, L.stream, Xc, psi,
-                         occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                         want_e ? 1 : 0, tw, md);
-    else
-      hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, 4>), grid, dim3(NT), 0, L.stream, Xc, psi,
-                         occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                         want_e ? 1 : 0, tw, md);
-    return hipGetLastError();
+      constexpr int ZB = 16;
+      constexpr int NT = ZB * 16;
+      constexpr int TM = pass_c_tile<N>();
+      if (tmax > TM) return hipErrorInvalidValue;
+      dim3 grid(N * (N / ZB), ntiles);
+      auto* Xc = static_cast<const cpx<T>*>(X);
+      auto* tw = static_cast<const cpx<T>*>(tb.tw);
+      auto* md = static_cast<const cpx<T>*>(tb.md);
+      if (L.ncls == 2)
+        hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
+                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
+                           want_e ? 1 : 0, tw, md);
+      else
+        hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
+                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
+                           want_e ? 1 : 0, tw, md);
+      return hipGetLastError();
     }
   });
 }

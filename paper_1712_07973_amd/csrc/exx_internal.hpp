@@ -10,37 +10,9 @@
 #include <vector>
 
 #include "../../include/exx.h"
+#include "exx_schedule.hpp"
 
 namespace exx {
-
-// One packed slot = two unordered pairs (ia, ja) and (ib, jb) sharing one
-// complex transform (real part: pair a, imaginary part: pair b); ib < 0 marks
-// an empty second half.  Slots are grouped by pair tile.
-struct Slot {
-  int ia, ja, ib, jb;
-};
-
-// One pair tile: orbitals [I0, I0+nI) x [J0, J0+nJ) (upper triangle when
-// diag), its slots [s0, s1).
-struct TilePair {
-  int s0, s1, I0, nI, J0, nJ, diag, pad;
-};
-
-struct Schedule {
-  int n_orb = 0;
-  int tile = 0;
-  int batch_slots = 0;
-  long long n_pairs = 0;
-  std::vector<Slot> slots;
-  std::vector<TilePair> tiles;
-  // launch chunks: [tile_begin, tile_end) with slots [slot_begin, slot_end)
-  struct Chunk {
-    int t0, t1, s0, s1;
-  };
-  std::vector<Chunk> chunks;
-  Slot* d_slots = nullptr;
-  TilePair* d_tiles = nullptr;
-};
 
 // Device tables of one plan (precision-specific arrays are null when unused).
 struct Tables {
@@ -69,6 +41,14 @@ struct exx_plan {
   exx_tuning tuning{};
   exx::Tables tables;
   std::map<int, exx::Schedule> schedules;  // keyed by n_orb (schedule depends on tuning.tile)
+  // profiling: event pairs recorded around launches, consumed by exx_plan_read_profile
+  bool profile = false;
+  bool recording = false;  // false while the stream is being captured
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
+  double prof_ms[EXX_PASS_KINDS] = {};
+  long long prof_launches[EXX_PASS_KINDS] = {};
 };
 
 namespace exx {
@@ -94,6 +74,7 @@ hipError_t launch_finalize(const Slot* slots, int nslots, const double* occ, con
                            double* pair_e, hipStream_t s);
 
 bool fused_supported(int precision, int n);
+int pass_c_max_tile(int n);  // largest pair-tile edge pass C supports at grid n
 
 // ---- plain FP64 path, exx_plain.hip ---------------------------------------
 hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs_in_launch,

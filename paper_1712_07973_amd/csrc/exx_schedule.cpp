@@ -1,0 +1,103 @@
+// exx_schedule.cpp -- pair schedule of one evaluation (host only).
+//
+// Pair-sum scheme of arXiv:1712.07973 (Section 2, Eq. 5): every unordered
+// pair i <= j is solved once.
+#include "exx_schedule.hpp"
+
+#include <algorithm>
+
+namespace exx {
+
+// Orbital tiles of edge T; tile pairs (I <= J) in rounds of a round-robin
+// tournament (the diagonal pairs (I, I) form one extra round), so the tile
+// pairs of one round share no orbital.  This is the single-device image of the
+// round-robin pair distribution of Section 2.1: there every process pairs its
+// orbitals with those received at step s; here each round is a set of
+// independent blocks that can update K psi without atomics.
+std::vector<std::vector<std::pair<int, int>>> tile_rounds(int nt) {
+  std::vector<std::vector<std::pair<int, int>>> rounds;
+  std::vector<std::pair<int, int>> diag;
+  for (int I = 0; I < nt; ++I) diag.push_back({I, I});
+  rounds.push_back(diag);
+  const int M = nt + (nt % 2);  // even number of teams; team M-1 is a bye when nt is odd
+  for (int r = 0; r + 1 < M; ++r) {
+    std::vector<std::pair<int, int>> rd;
+    auto add = [&](int a, int b) {
+      if (a >= nt || b >= nt || a == b) return;
+      rd.push_back({std::min(a, b), std::max(a, b)});
+    };
+    add(r, M - 1);
+    for (int k = 1; k < M / 2; ++k) add((r + k) % (M - 1), (r - k + (M - 1)) % (M - 1));
+    if (!rd.empty()) rounds.push_back(rd);
+  }
+  return rounds;
+}
+
+void build_schedule_host(int N, int T, int batch_slots, bool packed, Schedule& s) {
+  s = Schedule();
+  s.n_orb = N;
+  s.n_pairs = (long long)N * (N + 1) / 2;
+  s.batch_slots = batch_slots;
+  if (!packed) {
+    s.tile = 0;
+    for (int i = 0; i < N; ++i)
+      for (int j = i; j < N; ++j) s.slots.push_back({i, j, -1, -1});
+    int cap = std::max(1, batch_slots);
+    for (int s0 = 0; s0 < (int)s.slots.size(); s0 += cap)
+      s.chunks.push_back({0, 0, s0, std::min<int>((int)s.slots.size(), s0 + cap), 0, 0});
+    return;
+  }
+  T = std::max(1, T);
+  s.tile = T;
+  const int nt = (N + T - 1) / T;
+  auto rounds = tile_rounds(nt);
+  s.n_rounds = (int)rounds.size();
+  std::vector<int> round_of;
+  for (size_t r = 0; r < rounds.size(); ++r)
+    for (auto [I, J] : rounds[r]) {
+      TilePair tp{};
+      tp.I0 = I * T;
+      tp.nI = std::min(T, N - tp.I0);
+      tp.J0 = J * T;
+      tp.nJ = std::min(T, N - tp.J0);
+      tp.diag = (I == J);
+      std::vector<std::pair<int, int>> pairs;
+      for (int a = 0; a < tp.nI; ++a)
+        for (int b = tp.diag ? a : 0; b < tp.nJ; ++b) pairs.push_back({tp.I0 + a, tp.J0 + b});
+      tp.s0 = (int)s.slots.size();
+      for (size_t k = 0; k < pairs.size(); k += 2) {
+        Slot sl{pairs[k].first, pairs[k].second, -1, -1};
+        if (k + 1 < pairs.size()) {
+          sl.ib = pairs[k + 1].first;
+          sl.jb = pairs[k + 1].second;
+        }
+        s.slots.push_back(sl);
+      }
+      tp.s1 = (int)s.slots.size();
+      s.tiles.push_back(tp);
+      round_of.push_back((int)r);
+    }
+  // chunks of whole tile pairs whose slots fit the launch capacity; pass C
+  // segments split chunks at round boundaries
+  const int maxtp = (T * (T + 1)) / 2;
+  const int cap = std::max(batch_slots, (maxtp + 1) / 2);
+  int t0 = 0;
+  while (t0 < (int)s.tiles.size()) {
+    int t1 = t0;
+    while (t1 < (int)s.tiles.size() && s.tiles[t1].s1 - s.tiles[t0].s0 <= cap) ++t1;
+    if (t1 == t0) t1 = t0 + 1;
+    Schedule::Chunk c{t0, t1, s.tiles[t0].s0, s.tiles[t1 - 1].s1, (int)s.segments.size(), 0};
+    int a = t0;
+    while (a < t1) {
+      int b = a;
+      while (b < t1 && round_of[b] == round_of[a]) ++b;
+      s.segments.push_back({a, b});
+      a = b;
+    }
+    c.seg1 = (int)s.segments.size();
+    s.chunks.push_back(c);
+    t0 = t1;
+  }
+}
+
+}  // namespace exx

@@ -1,0 +1,55 @@
+// exx_schedule.hpp -- pair schedule of one evaluation (host only, no HIP).
+#pragma once
+
+#include <utility>
+#include <vector>
+
+namespace exx {
+
+// One packed slot = two unordered pairs (ia, ja) and (ib, jb) sharing one
+// complex transform (real part: pair a, imaginary part: pair b); ib < 0 marks
+// an empty second half.  Slots are grouped by pair tile.
+struct Slot {
+  int ia, ja, ib, jb;
+};
+
+// One pair tile: orbitals [I0, I0+nI) x [J0, J0+nJ) (upper triangle when
+// diag), its slots [s0, s1).
+struct TilePair {
+  int s0, s1, I0, nI, J0, nJ, diag, pad;
+};
+
+struct Schedule {
+  int n_orb = 0;
+  int tile = 0;
+  int batch_slots = 0;
+  long long n_pairs = 0;
+  std::vector<Slot> slots;
+  std::vector<TilePair> tiles;
+  // launch chunks: tiles [t0, t1) with slots [s0, s1); pass C is launched once
+  // per segment [seg0, seg1) of `segments`, each a run of orbital-disjoint tiles
+  struct Chunk {
+    int t0, t1, s0, s1, seg0, seg1;
+  };
+  struct Segment {
+    int t0, t1;
+  };
+  std::vector<Chunk> chunks;
+  std::vector<Segment> segments;
+  int n_rounds = 0;
+  Slot* d_slots = nullptr;
+  TilePair* d_tiles = nullptr;
+};
+
+// Builds the schedule for n_orb orbitals.
+//   packed = false: one pair per slot in (i <= j) order, chunks of batch_slots
+//                   (the plain path);
+//   packed = true : tiles of edge `tile`, tile pairs in round-robin rounds, two
+//                   pairs per slot, chunks of whole tile pairs within batch_slots.
+void build_schedule_host(int n_orb, int tile, int batch_slots, bool packed, Schedule& s);
+
+// Rounds of a round-robin tournament over nt tiles; the first round holds the
+// diagonal pairs (I, I).  No two pairs of one round share a tile.
+std::vector<std::vector<std::pair<int, int>>> tile_rounds(int nt);
+
+}  // namespace exx

@@ -1,0 +1,102 @@
+"""Autograd of E_x through the HIP library.
+
+* the backward (recomputed K psi) equals the oracle gradient -2 f h^3 K psi;
+* directional finite differences of the GPU forward (Richardson, exact for a
+  quartic up to rounding) agree with the backward on 4 orbitals of a
+  periodic system of p-type Gaussians;
+* the occupation gradient -sum_j f_j e_kj against central differences
+  (exact for a quadratic);
+* the FP32 backward against the FP64 backward.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import TOL_FP32_K, grid_of, oracle_result, say, small_system
+
+pytestmark = pytest.mark.gpu
+
+exx = pytest.importorskip("paper_1712_07973_amd")
+
+
+def _tensors(s, requires_grad=True):
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev).requires_grad_(requires_grad)
+    occ = torch.from_numpy(s.occ).to(dev).requires_grad_(requires_grad)
+    return psi, occ
+
+
+@pytest.mark.parametrize("precision", ["fp64_fused", "fp64_plain"])
+def test_backward_equals_oracle_gradient(precision):
+    say(f"[autograd] oracle gradient {precision}")
+    s, ref = oracle_result("free", 32, 6, 23, 0)
+    psi, occ = _tensors(s)
+    E = exx.exchange_energy(psi, occ, grid_of(s), precision)
+    E.backward()
+    g_ref = oracle.exx_grad_psi(ref["kpsi"], s.occ, s.h)
+    go_ref = oracle.exx_grad_occ(ref["pair_e"], s.occ)
+    assert E.item() == pytest.approx(ref["E"], rel=1e-12)
+    g = psi.grad.cpu().numpy()
+    assert np.max(np.abs(g - g_ref)) <= 1e-11 * np.max(np.abs(g_ref))
+    assert np.allclose(occ.grad.cpu().numpy(), go_ref, rtol=1e-11, atol=0)
+
+
+def test_finite_differences_on_four_orbitals():
+    say("[autograd] finite differences, periodic p-type")
+    s = small_system("periodic", 32, 6, seed=31, ptype=True)
+    g = grid_of(s)
+    psi, occ = _tensors(s)
+    E = exx.exchange_energy(psi, occ, g, "fp64_fused")
+    E.backward()
+    grad = psi.grad.detach()
+    rng = np.random.default_rng(3)
+    d = np.zeros_like(s.psi)
+    d[:4] = rng.normal(size=d[:4].shape)  # perturb orbitals 0..3 only
+    d = torch.from_numpy(d).to(psi.device)
+    with torch.no_grad():
+        def Ef(eps):
+            return exx.exchange_energy(psi + eps * d, occ, g, "fp64_fused").item()
+
+        def D(eps):
+            return (Ef(eps) - Ef(-eps)) / (2 * eps)
+
+        eps = 1e-3
+        fd = (4.0 * D(eps / 2) - D(eps)) / 3.0
+        an = float((grad * d).sum().item())
+    assert fd == pytest.approx(an, rel=1e-8)
+    # Euler identity for a homogeneous quartic: sum_k <psi_k, dE/dpsi_k> = 4 E
+    assert float((grad * psi.detach()).sum().item()) == pytest.approx(4.0 * E.item(), rel=1e-11)
+
+
+def test_occupation_gradient_finite_difference():
+    say("[autograd] occupation gradient")
+    s = small_system("free", 16, 4, seed=33, frac=2)
+    g = grid_of(s)
+    psi, occ = _tensors(s)
+    E = exx.exchange_energy(psi, occ, g, "fp64_plain")
+    E.backward()
+    with torch.no_grad():
+        for k in range(4):
+            df = torch.zeros_like(occ)
+            df[k] = 1e-2
+            Ep = exx.exchange_energy(psi, occ + df, g, "fp64_plain").item()
+            Em = exx.exchange_energy(psi, occ - df, g, "fp64_plain").item()
+            assert (Ep - Em) / 2e-2 == pytest.approx(occ.grad[k].item(), rel=1e-10)
+
+
+def test_fp32_backward_matches_fp64_backward():
+    say("[autograd] fp32 vs fp64 backward")
+    s = small_system("free", 48, 5, seed=35)
+    g = grid_of(s)
+    out = {}
+    for prec in ("fp32", "fp64_fused"):
+        psi, occ = _tensors(s)
+        E = exx.exchange_energy(psi, occ, g, prec)
+        E.backward()
+        out[prec] = (E.item(), psi.grad.cpu().numpy(), occ.grad.cpu().numpy())
+    assert abs(out["fp32"][0] - out["fp64_fused"][0]) / 5 < 1e-6
+    a, b = out["fp32"][1], out["fp64_fused"][1]
+    rel = np.linalg.norm((a - b).reshape(5, -1), axis=1) / np.linalg.norm(b.reshape(5, -1), axis=1)
+    assert rel.max() < TOL_FP32_K
+    assert np.allclose(out["fp32"][2], out["fp64_fused"][2], rtol=1e-6)

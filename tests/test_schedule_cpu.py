@@ -1,0 +1,98 @@
+"""The pair schedule (host code of libexx) built with g++ and checked on the CPU.
+
+* every unordered pair i <= j appears exactly once (N(N+1)/2 solves, Section 2);
+* packed slots hold two pairs of the same tile pair (at most one half-empty
+  slot per tile pair);
+* the tile pairs of one pass-C launch (a segment) share no orbital, which is
+  what lets pass C update K psi with plain read-modify-writes;
+* chunks cover the slots contiguously and respect the slot capacity.
+"""
+import itertools
+import os
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "paper_1712_07973_amd", "csrc", "exx_schedule.cpp")
+
+
+@pytest.fixture(scope="module")
+def probe(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("sched") / "probe")
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-o", exe,
+                        os.path.join(HERE, "schedule_probe.cpp"), SRC],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return exe
+
+
+def run(probe, N, T, cap, packed=True):
+    out = subprocess.run([probe, str(N), str(T), str(cap), "1" if packed else "0"],
+                         capture_output=True, text=True, check=True).stdout.split("\n")
+    rec = {"S": [], "T": [], "C": [], "G": []}
+    head = None
+    for line in out:
+        if not line:
+            continue
+        k, *v = line.split()
+        if k == "P":
+            head = tuple(int(x) for x in v)
+        else:
+            rec[k].append(tuple(int(x) for x in v))
+    return head, rec
+
+
+@pytest.mark.parametrize("N,T,cap", [(1, 8, 64), (5, 4, 3), (8, 8, 1 << 20), (32, 8, 1 << 20),
+                                     (33, 8, 40), (37, 4, 17), (64, 8, 100), (96, 4, 1 << 20)])
+def test_packed_schedule_invariants(probe, N, T, cap):
+    head, r = run(probe, N, T, cap)
+    assert head[0] == N * (N + 1) // 2
+    pairs = []
+    for ia, ja, ib, jb in r["S"]:
+        pairs.append((ia, ja))
+        if ib >= 0:
+            pairs.append((ib, jb))
+    assert sorted(pairs) == [(i, j) for i in range(N) for j in range(i, N)]
+    # slots of a tile pair belong to it; at most one half-empty slot per tile pair
+    for s0, s1, I0, nI, J0, nJ, diag in r["T"]:
+        half = 0
+        for ia, ja, ib, jb in r["S"][s0:s1]:
+            for i, j in ((ia, ja), (ib, jb)):
+                if i < 0:
+                    half += 1
+                    continue
+                assert I0 <= i < I0 + nI and J0 <= j < J0 + nJ
+        assert half <= 1
+    # segments are orbital-disjoint
+    for t0, t1 in r["G"]:
+        seen = set()
+        for s0, s1, I0, nI, J0, nJ, diag in r["T"][t0:t1]:
+            orbs = set(range(I0, I0 + nI)) | set(range(J0, J0 + nJ))
+            assert not (orbs & seen)
+            seen |= orbs
+    # chunks cover slots and tiles contiguously, within capacity when possible
+    s_prev, t_prev = 0, 0
+    for t0, t1, s0, s1, g0, g1 in r["C"]:
+        assert t0 == t_prev and s0 == s_prev
+        assert s1 - s0 <= max(cap, (T * (T + 1) // 2 + 1) // 2)
+        assert r["G"][g0][0] == t0 and r["G"][g1 - 1][1] == t1
+        t_prev, s_prev = t1, s1
+    assert s_prev == len(r["S"]) and t_prev == len(r["T"])
+
+
+def test_round_robin_round_count(probe):
+    # nt tiles: one diagonal round plus nt-1 (even nt) or nt (odd nt) rounds
+    for N, T in [(32, 8), (40, 8), (8, 8)]:
+        nt = -(-N // T)
+        head, _ = run(probe, N, T, 1 << 20)
+        expect = 1 + (nt - 1 if nt % 2 == 0 else nt) if nt > 1 else 1
+        assert head[2] == expect
+
+
+def test_plain_schedule_is_one_pair_per_slot(probe):
+    head, r = run(probe, 6, 0, 4, packed=False)
+    assert [s[:2] for s in r["S"]] == [(i, j) for i in range(6) for j in range(i, 6)]
+    assert all(s[2] == -1 for s in r["S"])
+    assert [c[2:4] for c in r["C"]] == [(0, 4), (4, 8), (8, 12), (12, 16), (16, 20), (20, 21)]
