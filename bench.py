@@ -109,6 +109,43 @@ def cpu_baseline(sysm, n_sample: int) -> dict:
                       f"(E_x and K psi), scipy.fft FP64 with workers={workers}, {dt:.1f} s"}
 
 
+def bench_batch(a, dev) -> int:
+    """Sixteen uneven isolated systems in one captured HIP graph (FP32 path)."""
+    import torch
+
+    import paper_1712_07973_amd as exx
+    from exx_inputs import batch_recipes, make_system, pair_count
+    systems = [make_system(r) for r in batch_recipes()]
+    grids = [exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R) for s in systems]
+    psis = [torch.from_numpy(s.psi).to(dev) for s in systems]
+    occs = [torch.from_numpy(s.occ).to(dev) for s in systems]
+    pairs = sum(pair_count(s.n_orb) for s in systems)
+    b = exx.Batch(grids, [s.n_orb for s in systems], "fp32", use_graph=True)
+    outs = None
+    for _ in range(max(1, a.warmup)):
+        outs = b.compute(psis, occs, outputs=outs)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(a.steps):
+        b.compute(psis, occs, outputs=outs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / a.steps
+    out = {"metric": METRIC, "value": round(pairs / (ms * 1e-3), 1), "unit": "pair-solves/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "16 isolated systems, n in {48..112} padded to 2n, N in [16,96], "
+                                  "one captured HIP graph per evaluation",
+                      "pairs": pairs, "systems": [[s.n, s.n_orb] for s in systems]},
+           "E_x": [float(o[0].item()) for o in outs]}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +156,8 @@ def main(argv=None) -> int:
     ap.add_argument("--no-baselines", action="store_true", help="skip the FP64 GPU paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=12)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device-to-device 3 times (calibrates memory counters)")
     a = ap.parse_args(argv)
 
     if a.gpus != 1:
@@ -137,6 +176,16 @@ def main(argv=None) -> int:
         return 2
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.copy_probe:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_per_launch": src.numel() * 4, "launches": 3}))
+        return 0
+    if a.workload == "batch16_free":
+        return bench_batch(a, dev)
     sysm = system(a.workload)
     N, n = sysm.n_orb, sysm.n
     pairs = pair_count(N)

@@ -1,9 +1,11 @@
 // exx_batch.cpp -- batches of independent systems and the autotuner.
 //
-// A batch owns one plan per distinct (grid, boundary, kernel) and evaluates
-// every system on one stream; with use_graph the whole sequence (all
-// systems, all passes) is captured once into a HIP graph and replayed, so a
-// batch costs one graph launch.  The autotuner times a small grid of tunings
+// A batch owns one plan per system and spreads the systems over a few side
+// streams forked from the caller's stream (event fork/join), so independent
+// systems overlap on the device; with use_graph the whole evaluation (all
+// systems, all passes, the fork and the join) is captured once into a HIP
+// graph with parallel branches and replayed, so a batch costs one graph
+// launch.  The autotuner times a small grid of tunings
 // with hipEvents and keeps the fastest; results persist in a text cache.
 #include <hip/hip_runtime.h>
 
@@ -31,7 +33,14 @@ struct exx_batch {
   unsigned captured_flags = 0;
   void* captured_ws = nullptr;
   hipStream_t captured_stream = nullptr;
+  std::vector<hipStream_t> side;  // default-priority, non-blocking
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
 };
+
+namespace {
+constexpr int kSideStreams = 4;
+}
 
 namespace {
 
@@ -78,6 +87,23 @@ int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, i
     off += (bytes + 255) / 256 * 256;
   }
   b->ws_total = off;
+  const int ns = std::min<int>(kSideStreams, n_systems);
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    exx_batch_destroy(b);
+    return EXX_ERR_HIP;
+  }
+  for (int k = 0; k < ns; ++k) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      if (st) (void)hipStreamDestroy(st);
+      exx_batch_destroy(b);
+      return EXX_ERR_HIP;
+    }
+    b->side.push_back(st);
+    b->join.push_back(ev);
+  }
   *out = b;
   return EXX_OK;
 }
@@ -87,6 +113,9 @@ void exx_batch_destroy(exx_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   for (auto* p : b->plans) exx_plan_destroy(p);
+  for (auto st : b->side) (void)hipStreamDestroy(st);
+  for (auto ev : b->join) (void)hipEventDestroy(ev);
+  if (b->fork) (void)hipEventDestroy(b->fork);
   delete b;
 }
 
@@ -96,16 +125,34 @@ int exx_batch_workspace_bytes(const exx_batch* b, size_t* bytes) {
   return EXX_OK;
 }
 
-static int batch_eager(exx_batch* b, const exx_system* sys, int mode, unsigned flags, char* ws,
+// Issues every system: fork the side streams from st, system s on side stream
+// s mod K (largest systems first), join back into st.
+static int batch_issue(exx_batch* b, const exx_system* sys, int mode, unsigned flags, char* ws,
                        hipStream_t st) {
-  for (size_t s = 0; s < b->plans.size(); ++s) {
+  if (hipEventRecord(b->fork, st) != hipSuccess) return EXX_ERR_HIP;
+  for (auto side : b->side)
+    if (hipStreamWaitEvent(side, b->fork, 0) != hipSuccess) return EXX_ERR_HIP;
+  std::vector<size_t> order(b->plans.size());
+  for (size_t s = 0; s < order.size(); ++s) order[s] = s;
+  auto work = [&](size_t s) {
+    double n3 = (double)b->plans[s]->n * b->plans[s]->n * b->plans[s]->n * b->plans[s]->ncls;
+    return n3 * b->n_orb[s] * (b->n_orb[s] + 1);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t c) { return work(a) > work(c); });
+  int rc = EXX_OK;
+  for (size_t k = 0; k < order.size() && rc == EXX_OK; ++k) {
+    const size_t s = order[k];
     size_t bytes = 0;
     exx_workspace_bytes(b->plans[s], b->n_orb[s], &bytes);
-    int rc = exx_compute(b->plans[s], sys[s].psi, sys[s].occ, b->n_orb[s], mode, flags, sys[s].ex_out,
-                         sys[s].kpsi, sys[s].pair_e, ws + b->ws_off[s], bytes, st);
-    if (rc != EXX_OK) return rc;
+    rc = exx_compute(b->plans[s], sys[s].psi, sys[s].occ, b->n_orb[s], mode, flags, sys[s].ex_out,
+                     sys[s].kpsi, sys[s].pair_e, ws + b->ws_off[s], bytes,
+                     b->side[k % b->side.size()]);
   }
-  return EXX_OK;
+  for (size_t k = 0; k < b->side.size(); ++k) {
+    if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess) return EXX_ERR_HIP;
+    if (hipStreamWaitEvent(st, b->join[k], 0) != hipSuccess) return EXX_ERR_HIP;
+  }
+  return rc;
 }
 
 int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned flags, void* ws,
@@ -115,7 +162,7 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
   if (((uintptr_t)ws % 256) != 0) return EXX_ERR_ALIGNMENT;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* wsc = static_cast<char*>(ws);
-  if (!b->use_graph) return batch_eager(b, sys, mode, flags, wsc, st);
+  if (!b->use_graph) return batch_issue(b, sys, mode, flags, wsc, st);
   const size_t n = b->plans.size();
   bool reuse = b->exec && same_systems(b->captured, sys, n) && b->captured_mode == mode &&
                b->captured_flags == flags && b->captured_ws == ws && b->captured_stream == st;
@@ -134,7 +181,7 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
       if (own) (void)hipStreamDestroy(cs);
       return EXX_ERR_HIP;
     }
-    int rc = batch_eager(b, sys, mode, flags, wsc, cs);
+    int rc = batch_issue(b, sys, mode, flags, wsc, cs);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     if (own) (void)hipStreamDestroy(cs);

@@ -218,8 +218,10 @@ struct SlabFft {
       }
     }
   }
-  // y forward step 2: layout A -> layout B (ky in natural order)
-  static __device__ __forceinline__ void y_fwd2(cpx<T>* lds, int tid) {
+  // y forward step 2: layout A (src) -> layout B (dst), ky in natural order;
+  // in place (src == dst) every item is loaded before any is stored
+  template <bool INPLACE>
+  static __device__ __forceinline__ void y_fwd2(const cpx<T>* src, cpx<T>* dst, int tid) {
     cpx<T> w[I2][L2];
 #pragma unroll
     for (int ii = 0; ii < I2; ++ii) {
@@ -227,18 +229,18 @@ struct SlabFft {
       if (ok2(it)) {
         int z = it % N, q1 = it / N;
 #pragma unroll
-        for (int t = 0; t < L2; ++t) w[ii][t] = lds[(t + L2 * q1) * N + z];
+        for (int t = 0; t < L2; ++t) w[ii][t] = src[(t + L2 * q1) * N + z];
         Dft<L2, -1, T>::run(w[ii]);
       }
     }
-    __syncthreads();
+    if (INPLACE) __syncthreads();
 #pragma unroll
     for (int ii = 0; ii < I2; ++ii) {
       int it = tid + ii * NT;
       if (ok2(it)) {
         int z = it % N, q1 = it / N;
 #pragma unroll
-        for (int q2 = 0; q2 < L2; ++q2) lds[z * PB + q1 + L1 * q2] = w[ii][q2];
+        for (int q2 = 0; q2 < L2; ++q2) dst[z * PB + q1 + L1 * q2] = w[ii][q2];
       }
     }
   }
@@ -297,8 +299,10 @@ struct SlabFft {
     for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds[(t + L2 * q1) * PB + ky];
     Dft<L1, 1, T>::run(v);
   }
-  // y inverse step 2: layout B -> layout A
-  static __device__ __forceinline__ void y_inv2(cpx<T>* lds, const cpx<T>* tw, int tid) {
+  // y inverse step 2: layout B (src) -> layout A (dst)
+  template <bool INPLACE>
+  static __device__ __forceinline__ void y_inv2(const cpx<T>* src, cpx<T>* dst, const cpx<T>* tw,
+                                                int tid) {
     cpx<T> w[I2][L2];
 #pragma unroll
     for (int ii = 0; ii < I2; ++ii) {
@@ -306,20 +310,20 @@ struct SlabFft {
       if (ok2(it)) {
         int z = it % N, q1 = it / N;
 #pragma unroll
-        for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = lds[z * PB + q1 + L1 * q2];
+        for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = src[z * PB + q1 + L1 * q2];
         Dft<L2, 1, T>::run(w[ii]);
 #pragma unroll
         for (int t = 1; t < L2; ++t) w[ii][t] = cmulc(w[ii][t], tw[t * q1]);
       }
     }
-    __syncthreads();
+    if (INPLACE) __syncthreads();
 #pragma unroll
     for (int ii = 0; ii < I2; ++ii) {
       int it = tid + ii * NT;
       if (ok2(it)) {
         int z = it % N, q1 = it / N;
 #pragma unroll
-        for (int t = 0; t < L2; ++t) lds[(t + L2 * q1) * N + z] = w[ii][t];
+        for (int t = 0; t < L2; ++t) dst[(t + L2 * q1) * N + z] = w[ii][t];
       }
     }
   }
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
   constexpr int L1 = F::L1, L2 = F::L2, PB = F::PB, I1 = F::I1;
   constexpr int M = NCLS * N;
   constexpr int H = M / 2 + 1;
-  __shared__ cpx<T> lds[N * PB];
+  __shared__ cpx<T> lds[(SHARE_Y ? 2 : 1) * N * PB];
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
 
@@ -382,11 +386,15 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
   __syncthreads();
 
   if constexpr (SHARE_Y) {
+    // two LDS buffers U, V: every step reads one and writes the other (or
+    // registers), which removes the in-place and write-after-read barriers
+    cpx<T>* U = lds;
+    cpx<T>* Vb = lds + N * PB;
 #pragma unroll 1
     for (int cy = 0; cy < NCLS; ++cy) {
-      F::y_fwd1(g, lds, tw, md, cy, 0, tid);
+      F::y_fwd1(g, U, tw, md, cy, 0, tid);
       __syncthreads();
-      F::y_fwd2(lds, tid);
+      F::template y_fwd2<false>(U, Vb, tid);
       __syncthreads();
       cpx<T> yv[I1][L1];
       cpx<T> wacc[I1][L1];
@@ -397,14 +405,14 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
           int ky = it % N, t = it / N;
 #pragma unroll
           for (int k1 = 0; k1 < L1; ++k1) {
-            yv[ii][k1] = lds[(t + L2 * k1) * PB + ky];
+            yv[ii][k1] = Vb[(t + L2 * k1) * PB + ky];
             wacc[ii][k1] = {T(0), T(0)};
           }
         }
       }
-      __syncthreads();
-#pragma unroll 1
+#pragma unroll
       for (int cz = 0; cz < NCLS; ++cz) {
+        cpx<T>* B = cz ? Vb : U;  // class cz works in its own buffer
 #pragma unroll
         for (int ii = 0; ii < I1; ++ii) {
           int it = tid + ii * NT;
@@ -414,11 +422,11 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
 #pragma unroll
             for (int k1 = 0; k1 < L1; ++k1)
               v[k1] = cz ? cmul(yv[ii][k1], md[t + L2 * k1]) : yv[ii][k1];
-            F::z_fwd1_item(v, lds, tw, ky, t);
+            F::z_fwd1_item(v, B, tw, ky, t);
           }
         }
         __syncthreads();
-        F::template z_mid<EONLY, M>(lds, tw, kt, cy, cz, esum, tid);
+        F::template z_mid<EONLY, M>(B, tw, kt, cy, cz, esum, tid);
         __syncthreads();
         if (EONLY) continue;
 #pragma unroll
@@ -427,29 +435,32 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
           if (F::ok1(it)) {
             int ky = it % N, t = it / N;
             cpx<T> v[L1];
-            F::z_inv1_item(v, lds, ky, t);
+            F::z_inv1_item(v, B, ky, t);
 #pragma unroll
             for (int k1 = 0; k1 < L1; ++k1)
               wacc[ii][k1] = cadd(wacc[ii][k1], cz ? cmulc(v[k1], md[t + L2 * k1]) : v[k1]);
           }
         }
-        __syncthreads();
       }
-      if (EONLY) continue;
+      if (EONLY) {
+        __syncthreads();
+        continue;
+      }
+      // U was last read by the cz = 0 inverse step, before the previous barrier
 #pragma unroll
       for (int ii = 0; ii < I1; ++ii) {
         int it = tid + ii * NT;
         if (F::ok1(it)) {
           int ky = it % N, t = it / N;
 #pragma unroll
-          for (int k1 = 0; k1 < L1; ++k1) lds[(t + L2 * k1) * PB + ky] = wacc[ii][k1];
+          for (int k1 = 0; k1 < L1; ++k1) U[(t + L2 * k1) * PB + ky] = wacc[ii][k1];
         }
       }
       __syncthreads();
-      F::y_inv2(lds, tw, tid);
+      F::template y_inv2<false>(U, Vb, tw, tid);
       __syncthreads();
-      F::y_inv1(lds, md, cy, 0, acc, tid);
-      __syncthreads();
+      F::y_inv1(Vb, md, cy, 0, acc, tid);
+      // the next y_fwd1 writes U, whose last reads (y_inv2) precede the barrier above
     }
   } else {
 #pragma unroll 1
@@ -458,7 +469,7 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
       const int cz = NCLS == 2 ? (cls & 1) : 0;
       F::y_fwd1(g, lds, tw, md, cy, cz, tid);
       __syncthreads();
-      F::y_fwd2(lds, tid);
+      F::template y_fwd2<true>(lds, lds, tid);
       __syncthreads();
 #pragma unroll
       for (int ii = 0; ii < I1; ++ii) {
@@ -487,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
         }
       }
       __syncthreads();
-      F::y_inv2(lds, tw, tid);
+      F::template y_inv2<true>(lds, lds, tw, tid);
       __syncthreads();
       F::y_inv1(lds, md, cy, cz, acc, tid);
       __syncthreads();
@@ -565,14 +576,18 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
   constexpr int NL = NCLS * ZB;
-  constexpr int NO = 2 * TM;                 // orbitals per tile pair (I then J)
+  constexpr int NO = 2 * TM;                  // orbitals per tile pair (I then J)
   constexpr int NW = NT / 64;
-  constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched values per thread
+  constexpr int MAXS = (TM * TM + 1) / 2;     // slots per tile pair
+  constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
   static_assert(ZB * L2 == NT, "one point-owner item per thread");
-  __shared__ cpx<T> xs[NL * P];
+  __shared__ cpx<T> xs[2][NL * P];  // spectrum rows, double buffered
+  __shared__ cpx<T> xo[NL * P];     // after the inverse step 2
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
-  __shared__ double ered[NW][2];
+  __shared__ Slot st[MAXS];
+  __shared__ double fo[NO];
+  __shared__ double ered[MAXS][2][NW];
 
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
@@ -581,10 +596,17 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   const size_t M3 = (size_t)N * N * N;
   const int t_own = tid % L2, zi_own = tid / L2;
   const size_t row = ((size_t)(z0 + zi_own) * N + y) * N;  // offset of the owned row
+  const int ns = tp.s1 - tp.s0;
 
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
+  }
+  for (int k = tid; k < ns; k += NT) st[k] = slots[tp.s0 + k];
+  for (int k = tid; k < NO; k += NT) {
+    int o = k < TM ? tp.I0 + k : tp.J0 + (k - TM);
+    bool live = k < TM ? k < tp.nI : (!tp.diag && k - TM < tp.nJ);
+    fo[k] = live ? occ[o] : 0.0;
   }
   double acc[NO][L1];
 #pragma unroll
@@ -605,45 +627,58 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
       }
     }
   };
-  if (tp.s0 < tp.s1) fetch(tp.s0);
+  // orbital values of a slot at the owned points
+  T ps[4][L1];
+  auto fetch_psi = [&](const Slot& sl) {
+    const int o[4] = {sl.ia, sl.ja, sl.ib >= 0 ? sl.ib : sl.ia, sl.ib >= 0 ? sl.jb : sl.ja};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T* po = psi + (size_t)o[q] * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) ps[q][k1] = po[t_own + L2 * k1];
+    }
+  };
+  if (ns > 0) {
+    fetch(tp.s0);
+    fetch_psi(slots[tp.s0]);
+  }
+  __syncthreads();
+  auto loc = [&](int o) { return (o >= tp.I0 && o < tp.I0 + tp.nI) ? o - tp.I0 : TM + (o - tp.J0); };
 
 #pragma unroll 1
-  for (int s = tp.s0; s < tp.s1; ++s) {
+  for (int k = 0; k < ns; ++k) {
+    cpx<T>* xb = xs[k & 1];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      int p = tid + k * NT;
+    for (int q = 0; q < PF; ++q) {
+      int p = tid + q * NT;
       if ((NL * N) % NT == 0 || p < NL * N) {
         int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
-        xs[(cx * ZB + zi) * P + kx] = pf[k];
+        xb[(cx * ZB + zi) * P + kx] = pf[q];
       }
     }
-    if (s + 1 < tp.s1) fetch(s + 1);
+    T cur[4][L1];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) cur[q][k1] = ps[q][k1];
+    if (k + 1 < ns) {
+      fetch(tp.s0 + k + 1);
+      fetch_psi(st[k + 1]);
+    }
     __syncthreads();
-    // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle
+    // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle; xb -> xo
     constexpr int C2 = NL * L1;
-    constexpr int I2 = (C2 + NT - 1) / NT;
-    cpx<T> w[I2][L2];
 #pragma unroll
-    for (int ii = 0; ii < I2; ++ii) {
-      int it = tid + ii * NT;
-      if (C2 % NT == 0 || it < C2) {
-        int line = it % NL, q1 = it / NL;
+    for (int it = tid; it < C2; it += NT) {
+      int line = it % NL, q1 = it / NL;
+      cpx<T> w[L2];
 #pragma unroll
-        for (int q2 = 0; q2 < L2; ++q2) w[ii][q2] = xs[line * P + q1 + L1 * q2];
-        Dft<L2, 1, T>::run(w[ii]);
+      for (int q2 = 0; q2 < L2; ++q2) w[q2] = xb[line * P + q1 + L1 * q2];
+      Dft<L2, 1, T>::run(w);
 #pragma unroll
-        for (int t = 1; t < L2; ++t) w[ii][t] = cmulc(w[ii][t], tw[t * q1]);
-      }
-    }
-    __syncthreads();
+      for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q1]);
 #pragma unroll
-    for (int ii = 0; ii < I2; ++ii) {
-      int it = tid + ii * NT;
-      if (C2 % NT == 0 || it < C2) {
-        int line = it % NL, q1 = it / NL;
-#pragma unroll
-        for (int t = 0; t < L2; ++t) xs[line * P + t + L2 * q1] = w[ii][t];
-      }
+      for (int t = 0; t < L2; ++t) xo[line * P + t + L2 * q1] = w[t];
     }
     __syncthreads();
     // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b
@@ -651,60 +686,54 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
     {
       cpx<T> v[L1];
 #pragma unroll
-      for (int q1 = 0; q1 < L1; ++q1) v[q1] = xs[zi_own * P + t_own + L2 * q1];
+      for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
       Dft<L1, 1, T>::run(v);
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) V[k1] = v[k1];
       if (NCLS == 2) {
 #pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xs[(ZB + zi_own) * P + t_own + L2 * q1];
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
         Dft<L1, 1, T>::run(v);
 #pragma unroll
         for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
       }
     }
-    // reductions at the owned points; slot data are uniform (scalar registers)
-    const int ia = __builtin_amdgcn_readfirstlane(slots[s].ia);
-    const int ja = __builtin_amdgcn_readfirstlane(slots[s].ja);
-    const int ib = __builtin_amdgcn_readfirstlane(slots[s].ib);
-    const int jb = __builtin_amdgcn_readfirstlane(slots[s].jb);
-    const bool hb = ib >= 0;
-    auto loc = [&](int o) { return (o >= tp.I0 && o < tp.I0 + tp.nI) ? o - tp.I0 : TM + (o - tp.J0); };
+    // reductions at the owned points (slot data uniform across the block)
+    const Slot sl = st[k];
+    const bool hb = sl.ib >= 0;
+    const int la_i = loc(sl.ia), la_j = loc(sl.ja);
     double ea = 0.0, eb = 0.0;
     {
-      const T* pi = psi + (size_t)ia * M3 + row;
-      const T* pj = psi + (size_t)ja * M3 + row;
       double vi[L1], vj[L1];
+      const double fi = fo[la_i], fj = fo[la_j];
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
-        const int x = t_own + L2 * k1;
-        const T a = pi[x], b = pj[x];
+        const T a = cur[0][k1], b = cur[1][k1];
         const double Va = (double)V[k1].x;
         ea += (double)(a * b) * Va;
-        vi[k1] = occ[ja] * Va * (double)b;  // into (K psi)_ia
-        vj[k1] = occ[ia] * Va * (double)a;  // into (K psi)_ja
+        vi[k1] = fj * Va * (double)b;  // into (K psi)_ia
+        vj[k1] = fi * Va * (double)a;  // into (K psi)_ja
       }
       if (want_k) {
-        acc_add<NO, L1>(acc, loc(ia), vi);
-        if (ia != ja) acc_add<NO, L1>(acc, loc(ja), vj);
+        acc_add<NO, L1>(acc, la_i, vi);
+        if (sl.ia != sl.ja) acc_add<NO, L1>(acc, la_j, vj);
       }
     }
     if (hb) {
-      const T* pi = psi + (size_t)ib * M3 + row;
-      const T* pj = psi + (size_t)jb * M3 + row;
+      const int lb_i = loc(sl.ib), lb_j = loc(sl.jb);
       double vi[L1], vj[L1];
+      const double fi = fo[lb_i], fj = fo[lb_j];
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
-        const int x = t_own + L2 * k1;
-        const T a = pi[x], b = pj[x];
+        const T a = cur[2][k1], b = cur[3][k1];
         const double Vb = (double)V[k1].y;
         eb += (double)(a * b) * Vb;
-        vi[k1] = occ[jb] * Vb * (double)b;
-        vj[k1] = occ[ib] * Vb * (double)a;
+        vi[k1] = fj * Vb * (double)b;
+        vj[k1] = fi * Vb * (double)a;
       }
       if (want_k) {
-        acc_add<NO, L1>(acc, loc(ib), vi);
-        if (ib != jb) acc_add<NO, L1>(acc, loc(jb), vj);
+        acc_add<NO, L1>(acc, lb_i, vi);
+        if (sl.ib != sl.jb) acc_add<NO, L1>(acc, lb_j, vj);
       }
     }
     if (want_e) {
@@ -714,19 +743,23 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
         eb += __shfl_xor(eb, off);
       }
       if ((tid & 63) == 0) {
-        ered[tid >> 6][0] = ea;
-        ered[tid >> 6][1] = eb;
+        ered[k][0][tid >> 6] = ea;
+        ered[k][1][tid >> 6] = eb;
       }
     }
-    __syncthreads();
-    if (want_e && tid < 2) {
+  }
+  __syncthreads();
+  if (want_e) {
+    // one atomic per (slot half, block); other blocks add the other rows
+    for (int q = tid; q < 2 * ns; q += NT) {
+      const int k = q >> 1, half = q & 1;
+      if (half && st[k].ib < 0) continue;
       double sum = 0.0;
 #pragma unroll
-      for (int w2 = 0; w2 < NW; ++w2) sum += ered[w2][tid];
-      if (tid == 0 || hb) atomicAdd(&e_slot[2 * s + tid], sum);
+      for (int w2 = 0; w2 < NW; ++w2) sum += ered[k][half][w2];
+      atomicAdd(&e_slot[2 * (tp.s0 + k) + half], sum);
     }
   }
-
   if (!want_k) return;
   // K psi += partial sums; the launch's tile pairs are orbital-disjoint
 #pragma unroll

@@ -95,3 +95,25 @@ def periodic_gaussian_pair_energy(Q: float, c: float, L: float, kmax: int) -> fl
     nz = G2 > 0
     terms = (Q * Q) * np.exp(-G2[nz] * c * c) / G2[nz]
     return 4.0 * math.pi / L ** 3 * math.fsum(np.sort(terms).tolist())
+
+
+def screened_self_energy_normalised(c: float, omega: float) -> float:
+    """int int N(c) N(c) erfc(omega |r - r'|) / |r - r'| in free space.
+
+    erf(omega r)/r is the Coulomb potential of a Gaussian of variance
+    1/(2 omega^2), so the erf part is the Coulomb self energy of width
+    sqrt(2 c^2 + 1/(2 omega^2)) per axis for the difference coordinate.
+    """
+    return 2.0 / math.sqrt(math.pi) * (1.0 / math.sqrt(4.0 * c * c)
+                                       - 1.0 / math.sqrt(4.0 * c * c + 1.0 / (omega * omega)))
+
+
+def periodic_screened_pair_energy(Q: float, c: float, L: float, omega: float, kmax: int) -> float:
+    """(1/Omega) sum_G K_omega(G) |rho^(G)|^2 with K_omega = 4 pi (1 - e^{-G^2/4w^2}) / G^2, K(0) = pi/w^2."""
+    k = np.arange(-kmax, kmax + 1)
+    KX, KY, KZ = np.meshgrid(k, k, k, indexing="ij")
+    G2 = (2.0 * math.pi / L) ** 2 * (KX ** 2 + KY ** 2 + KZ ** 2).astype(np.float64)
+    nz = G2 > 0
+    terms = (Q * Q) * np.exp(-G2[nz] * c * c) * 4.0 * math.pi * (-np.expm1(-G2[nz] / (4 * omega ** 2))) / G2[nz]
+    total = math.fsum(np.sort(terms).tolist()) + Q * Q * math.pi / omega ** 2
+    return total / L ** 3

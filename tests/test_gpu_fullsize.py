@@ -1,0 +1,105 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py uses.
+
+The FP64 oracle would take minutes to hours here, so it is compared on what
+it can compute one by one: sampled pair energies and K psi rows at sampled
+points (stored by tests/golden/make_oracle_golden.py, which calls only the
+oracle), plus E_x and all pair energies for the 32-orbital workload.
+Properties that hold at any size are checked on the whole output:
+E_x = -1/2 h^3 sum_i f_i <psi_i, (K psi)_i>, a symmetric non-negative
+pair-energy matrix, and E_x = -1/2 sum f_i f_j e_ij.
+"""
+import functools
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import say
+
+pytestmark = pytest.mark.gpu
+
+exx = pytest.importorskip("paper_1712_07973_amd")
+from exx_inputs import batch_recipes, make_system, system  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = {"fp32": 1e-5, "fp64_fused": 1e-11, "fp64_plain": 1e-11}
+
+
+def golden(name):
+    path = os.path.join(GOLDEN, f"{name}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return dict(np.load(path))
+
+
+@functools.lru_cache(maxsize=2)
+def load_system(name):
+    if name.startswith("batch16_s"):
+        return make_system(batch_recipes()[int(name.split("_s")[1])])
+    return system(name)
+
+
+def evaluate(s, precision):
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    g = exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc == "free" else None)
+    plan = exx.Plan(g, precision, n_orb_max=s.n_orb)
+    pe = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=dev)
+    ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)
+    torch.cuda.synchronize()
+    # E_x from K psi: -1/2 h^3 sum_i f_i <psi_i, (K psi)_i>
+    dots = (psi.reshape(s.n_orb, -1) * kpsi.reshape(s.n_orb, -1)).sum(dim=1)
+    e_from_k = float(-0.5 * s.h ** 3 * (occ * dots).sum().item())
+    out = {"E": float(ex.item()), "E_from_kpsi": e_from_k, "pair_e": pe.cpu().numpy(),
+           "kpsi": kpsi}
+    del psi
+    return out
+
+
+def check(name, precision):
+    g = golden(name)
+    say(f"[fullsize] {name} {precision}")
+    s = load_system(name)
+    r = evaluate(s, precision)
+    tol = TOL[precision]
+    P = r["pair_e"]
+    scale = float(np.max(np.abs(P)))
+    assert np.array_equal(P, P.T)
+    assert P.min() > -tol * scale
+    assert r["E"] < 0
+    f = s.occ
+    assert r["E"] == pytest.approx(-0.5 * float(f @ P @ f), rel=1e-12)
+    assert r["E_from_kpsi"] == pytest.approx(r["E"], rel=max(tol, 1e-12))
+    if "E" in g:
+        assert abs(r["E"] - float(g["E"])) / s.n_orb < (1e-6 if precision == "fp32" else 1e-12 * abs(float(g["E"])))
+        assert np.max(np.abs(P - g["pair_e"])) <= tol * scale
+    if "pairs" in g:
+        got = np.array([P[i, j] for i, j in g["pairs"]])
+        assert np.max(np.abs(got - g["pair_energies"])) <= tol * scale
+    k = r["kpsi"].reshape(s.n_orb, -1)
+    pts = torch.from_numpy(g["kpsi_points"]).to(k.device)
+    for row, vals in zip(g["kpsi_rows"], g["kpsi_values"]):
+        got = k[int(row)].index_select(0, pts).cpu().numpy()
+        assert np.max(np.abs(got - vals)) <= tol * np.max(np.abs(vals))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
+def test_free64_n32(precision):
+    check("free64_n32", precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused"])
+def test_periodic96_n128(precision):
+    check("periodic96_n128", precision)
+
+
+@pytest.mark.timeout(600)
+def test_free128_n256_fp32():
+    check("free128_n256", "fp32")
+
+
+@pytest.mark.parametrize("sidx", [0, 5, 11])
+def test_batch16_members(sidx):
+    check(f"batch16_s{sidx}", "fp32")
