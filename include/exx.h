@@ -135,6 +135,7 @@ typedef struct exx_tuning {
   int batch_slots; /* packed pair slots per pass launch (>= 1) */
   int zblock_a;    /* grid rows per workgroup in the pair-build / forward pass */
   int zblock_c;    /* grid rows per workgroup in the inverse / reduction pass */
+  int slab_threads; /* threads per slab workgroup of the y/z pass (256 or 512 at n = 64) */
 } exx_tuning;
 
 int exx_plan_get_tuning(const exx_plan* plan, exx_tuning* out);

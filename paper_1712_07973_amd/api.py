@@ -130,11 +130,12 @@ class Plan:
         t = L.ExxTuning()
         L.check(L.lib().exx_plan_get_tuning(self._h, C.byref(t)), "exx_plan_get_tuning")
         return {"tile": t.tile, "batch_slots": t.batch_slots, "zblock_a": t.zblock_a,
-                "zblock_c": t.zblock_c}
+                "zblock_c": t.zblock_c, "slab_threads": t.slab_threads}
 
     def set_tuning(self, tile: int = 0, batch_slots: int = 0, zblock_a: int = 0,
-                   zblock_c: int = 0) -> None:
-        t = L.ExxTuning(int(tile), int(batch_slots), int(zblock_a), int(zblock_c))
+                   zblock_c: int = 0, slab_threads: int = 0) -> None:
+        t = L.ExxTuning(int(tile), int(batch_slots), int(zblock_a), int(zblock_c),
+                        int(slab_threads))
         L.check(L.lib().exx_plan_set_tuning(self._h, C.byref(t)), "exx_plan_set_tuning")
 
     def enable_profiling(self, on: bool = True) -> None:

@@ -119,6 +119,7 @@ void default_tuning(exx_plan* p) {
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
   p->tuning.zblock_a = 16;
   p->tuning.zblock_c = 8;
+  p->tuning.slab_threads = 256;
 }
 
 void build_schedule(const exx_plan* p, int N, Schedule& s) {
@@ -133,7 +134,7 @@ int cap_slots(const exx_plan* p, const Schedule& s) {
 }
 
 struct WsLayout {
-  size_t psi32 = 0, e_slot = 0, X = 0, total = 0;
+  size_t psi32 = 0, e_slot = 0, e_part = 0, X = 0, total = 0;
 };
 
 WsLayout layout(const exx_plan* p, const Schedule& s) {
@@ -143,6 +144,8 @@ WsLayout layout(const exx_plan* p, const Schedule& s) {
   if (is_fp32(p)) off += align_up((size_t)s.n_orb * p->n * p->n * p->n * sizeof(float), 256);
   w.e_slot = off;
   off += align_up(2 * s.slots.size() * sizeof(double), 256);
+  w.e_part = off;
+  if (!is_plain(p)) off += align_up(2 * s.slots.size() * (size_t)energy_parts(p->n) * sizeof(double), 256);
   w.X = off;
   off += align_up((size_t)cap_slots(p, s) * slot_bytes(p), 256);
   w.total = off;
@@ -230,10 +233,11 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     psiT = psi;
   }
   double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
+  double* e_part = reinterpret_cast<double*>(ws + w.e_part);
+  const int kparts = energy_parts(p->n);
   void* X = ws + w.X;
   {
     EXX_PROF(EXX_PASS_ZERO);
-    if (want_e) EXX_HIP(launch_zero(e_slot, 2 * s.slots.size(), st));
     if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
   }
   Launch L{p->n, p->ncls, p->m, p->h3, st};
@@ -245,19 +249,21 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     }
     {
       EXX_PROF(EXX_PASS_B);
-      EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_slot, c.s0, p->tables));
+      EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_part, c.s0, p->tables, p->tuning.slab_threads));
     }
     if (!parseval) {
       for (int g = c.seg0; g < c.seg1; ++g) {
         const auto& sg = s.segments[g];
         EXX_PROF(EXX_PASS_C);
         EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0, c.s0,
-                                 kpsi, e_slot, want_k, want_e, p->tuning.zblock_c, s.tile, p->tables));
+                                 kpsi, e_part, want_k, want_e, p->tuning.zblock_c, s.tile, p->tables));
       }
     }
   }
   if (want_e) {
     EXX_PROF(EXX_PASS_FINALIZE);
+    const int count = parseval ? p->ncls * p->n : p->n * p->n / 16;
+    EXX_HIP(launch_slot_reduce(e_part, kparts, count, 2 * (int)s.slots.size(), e_slot, st));
     EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, parseval,
                             (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
   }
@@ -458,6 +464,7 @@ int exx_plan_set_tuning(exx_plan* p, const exx_tuning* t) {
   if (t->batch_slots) p->tuning.batch_slots = t->batch_slots;
   if (t->zblock_a) p->tuning.zblock_a = t->zblock_a;
   if (t->zblock_c) p->tuning.zblock_c = t->zblock_c;
+  if (t->slab_threads) p->tuning.slab_threads = t->slab_threads;
   return EXX_OK;
 }
 

@@ -220,15 +220,16 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
       auto bar = line.find('|');
       if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
       exx_tuning t{};
-      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d", &t.tile, &t.batch_slots, &t.zblock_a,
-                      &t.zblock_c) == 4)
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.tile, &t.batch_slots, &t.zblock_a,
+                      &t.zblock_c, &t.slab_threads) == 5)
         return exx_plan_set_tuning(p, &t);
     }
   }
   exx_tuning base = p->tuning, best = base;
   float best_ms = 1e30f;
   std::vector<int> tiles = {4, 8};
-  std::vector<int> batches = {32, 64, 128, 256, 1 << 20};
+  std::vector<int> batches = {64, 256, 1 << 20};
+  std::vector<int> slab_threads = {256, 512};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EXX_ERR_HIP;
   double* ex_dev = nullptr;
@@ -236,9 +237,11 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   int rc = EXX_OK;
   for (int t : tiles) {
     for (int bs : batches) {
+     for (int sth : slab_threads) {
       exx_tuning cand = base;
       cand.tile = t;
       cand.batch_slots = bs;
+      cand.slab_threads = sth;
       if (exx_plan_set_tuning(p, &cand) != EXX_OK) continue;
       size_t need = 0;
       if (exx_workspace_bytes(p, n_orb, &need) != EXX_OK || need > ws_bytes) continue;
@@ -257,6 +260,8 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
         best_ms = ms;
         best = cand;
       }
+     }
+     if (rc != EXX_OK) break;
     }
     if (rc != EXX_OK) break;
   }
@@ -268,7 +273,7 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key.str() << "|" << best.tile << " " << best.batch_slots << " " << best.zblock_a << " "
-      << best.zblock_c << "\n";
+      << best.zblock_c << " " << best.slab_threads << "\n";
   }
   return exx_plan_prepare(p, n_orb);
 }

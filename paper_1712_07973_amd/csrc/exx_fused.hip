@@ -352,11 +352,20 @@ struct SlabFft {
   }
 };
 
+// The wide (512-thread) shared-y variant asks for two blocks per CU, i.e. a
+// budget of 128 registers (4 waves per SIMD); other variants take the
+// compiler's choice.
+template <typename T, int N, int NT, bool SHARE_Y>
+constexpr int pass_b_min_waves() {
+  return (SHARE_Y && NT == 512 && sizeof(T) == 4) ? 4 : 1;
+}
+
 template <typename T, int N, int NCLS, int NT, bool EONLY, bool SHARE_Y>
-__global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* __restrict__ ktab,
+__global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k_pass_b(cpx<T>* __restrict__ X, const T* __restrict__ ktab,
                                                const cpx<T>* __restrict__ twg,
                                                const cpx<T>* __restrict__ mdg,
-                                               double* __restrict__ e_slot, int slot0) {
+                                               double* __restrict__ e_slot, int slot0,
+                                               int kparts) {
   using F = SlabFft<T, N, NT>;
   constexpr int L1 = F::L1, L2 = F::L2, PB = F::PB, I1 = F::I1;
   constexpr int M = NCLS * N;
@@ -516,7 +525,8 @@ __global__ __launch_bounds__(NT) void k_pass_b(cpx<T>* __restrict__ X, const T* 
     if (tid == 0) {
       double sum = 0.0;
       for (int w = 0; w < NT / 64; ++w) sum += red[w];
-      atomicAdd(&e_slot[2 * (slot0 + ls)], sum);
+      // one partial per (slot, slab); summed in a fixed order by k_slot_reduce
+      e_slot[(size_t)(2 * (slot0 + ls)) * kparts + slab] = sum;
     }
     return;
   } else {
@@ -571,7 +581,7 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
                                                int slot_base, double* __restrict__ kpsi,
                                                double* __restrict__ e_slot, int want_k,
                                                int want_e, const cpx<T>* __restrict__ twg,
-                                               const cpx<T>* __restrict__ mdg) {
+                                               const cpx<T>* __restrict__ mdg, int kparts) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
@@ -750,14 +760,15 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   }
   __syncthreads();
   if (want_e) {
-    // one atomic per (slot half, block); other blocks add the other rows
+    // one partial per (slot half, row block), summed in a fixed order later
     for (int q = tid; q < 2 * ns; q += NT) {
       const int k = q >> 1, half = q & 1;
-      if (half && st[k].ib < 0) continue;
       double sum = 0.0;
+      if (!(half && st[k].ib < 0)) {
 #pragma unroll
-      for (int w2 = 0; w2 < NW; ++w2) sum += ered[k][half][w2];
-      atomicAdd(&e_slot[2 * (tp.s0 + k) + half], sum);
+        for (int w2 = 0; w2 < NW; ++w2) sum += ered[k][half][w2];
+      }
+      e_slot[(size_t)(2 * (tp.s0 + k) + half) * kparts + blockIdx.x] = sum;
     }
   }
   if (!want_k) return;
@@ -771,6 +782,36 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
 #pragma unroll
     for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += acc[lo][k1];
   }
+}
+
+// ---------------------------------------------------------------------------
+// pair-energy partials: pass C writes one per (slot half, row block of 16
+// z-rows: n^2/16 of them), the energy-only pass B one per (slot, slab: at most
+// 2n); k_slot_reduce sums each slot half's partials in a fixed order, so the
+// energies do not depend on block scheduling.
+// ---------------------------------------------------------------------------
+int energy_parts(int n) { return std::max(n * n / 16, 2 * n); }
+
+__global__ __launch_bounds__(256) void k_slot_reduce(const double* __restrict__ parts, int kparts,
+                                                     int count, int nhalves,
+                                                     double* __restrict__ e_slot) {
+  const int lane = threadIdx.x & 63;
+  const int h = blockIdx.x * 4 + (threadIdx.x >> 6);  // one wave per slot half
+  if (h >= nhalves) return;
+  const double* p = parts + (size_t)h * kparts;
+  double sum = 0.0;
+  for (int k = lane; k < count; k += 64) sum += p[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if (lane == 0) e_slot[h] = sum;
+}
+
+hipError_t launch_slot_reduce(const double* parts, int kparts, int count, int nhalves,
+                              double* e_slot, hipStream_t s) {
+  if (nhalves <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slot_reduce, dim3((nhalves + 3) / 4), dim3(256), 0, s, parts, kparts, count,
+                     nhalves, e_slot);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -890,9 +931,35 @@ constexpr bool pass_b_share_y() {
   return sizeof(T) == 4 ? N <= 64 : N <= 32;
 }
 
+template <typename T, int N, int NT, bool SY>
+hipError_t launch_pass_b_nt(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
+                            double* e_slot, int slot0, const Tables& tb) {
+  auto* kt = static_cast<const T*>(tb.ktab);
+  auto* tw = static_cast<const cpx<T>*>(tb.tw);
+  auto* md = static_cast<const cpx<T>*>(tb.md);
+  if (L.ncls == 2) {
+    dim3 grid(2 * N, nslots);
+    if (energy_only)
+      hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, true, SY>), grid, dim3(NT), 0, L.stream, Xc, kt,
+                         tw, md, e_slot, slot0, energy_parts(N));
+    else
+      hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, false, SY>), grid, dim3(NT), 0, L.stream, Xc, kt,
+                         tw, md, e_slot, slot0, energy_parts(N));
+  } else {
+    dim3 grid(N, nslots);
+    if (energy_only)
+      hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, true, false>), grid, dim3(NT), 0, L.stream, Xc,
+                         kt, tw, md, e_slot, slot0, energy_parts(N));
+    else
+      hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, false, false>), grid, dim3(NT), 0, L.stream, Xc,
+                         kt, tw, md, e_slot, slot0, energy_parts(N));
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
-                         int slot0, const Tables& tb) {
+                         int slot0, const Tables& tb, int slab_threads) {
   if (nslots <= 0) return hipSuccess;
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
     if constexpr (sizeof(T) == 8 && N > 96) {
@@ -901,27 +968,12 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
       constexpr int NT = pass_b_threads<T, N>();
       constexpr bool SY = pass_b_share_y<T, N>();
       auto* Xc = static_cast<cpx<T>*>(X);
-      auto* kt = static_cast<const T*>(tb.ktab);
-      auto* tw = static_cast<const cpx<T>*>(tb.tw);
-      auto* md = static_cast<const cpx<T>*>(tb.md);
-      if (L.ncls == 2) {
-        dim3 grid(2 * N, nslots);
-        if (energy_only)
-          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, true, SY>), grid, dim3(NT), 0, L.stream, Xc,
-                             kt, tw, md, e_slot, slot0);
-        else
-          hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, false, SY>), grid, dim3(NT), 0, L.stream, Xc,
-                             kt, tw, md, e_slot, slot0);
-      } else {
-        dim3 grid(N, nslots);
-        if (energy_only)
-          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, true, false>), grid, dim3(NT), 0, L.stream,
-                             Xc, kt, tw, md, e_slot, slot0);
-        else
-          hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, false, false>), grid, dim3(NT), 0, L.stream,
-                             Xc, kt, tw, md, e_slot, slot0);
+      if constexpr (SY && NT == 256 && sizeof(T) == 4 && N == 64) {
+        // the 512-thread variant: one item per thread, 4 waves per SIMD
+        if (slab_threads == 512)
+          return launch_pass_b_nt<T, N, 512, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
       }
-      return hipGetLastError();
+      return launch_pass_b_nt<T, N, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
     }
   });
 }
@@ -961,11 +1013,11 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
       if (L.ncls == 2)
         hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                           want_e ? 1 : 0, tw, md);
+                           want_e ? 1 : 0, tw, md, energy_parts(N));
       else
         hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                           want_e ? 1 : 0, tw, md);
+                           want_e ? 1 : 0, tw, md, energy_parts(N));
       return hipGetLastError();
     }
   });
@@ -976,9 +1028,9 @@ template hipError_t launch_pass_a<float>(const Launch&, const float*, void*, con
 template hipError_t launch_pass_a<double>(const Launch&, const double*, void*, const Slot*, int,
                                           int, const double*, bool, int, const Tables&);
 template hipError_t launch_pass_b<float>(const Launch&, void*, int, bool, double*, int,
-                                         const Tables&);
+                                         const Tables&, int);
 template hipError_t launch_pass_b<double>(const Launch&, void*, int, bool, double*, int,
-                                          const Tables&);
+                                          const Tables&, int);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
                                          const Slot*, const TilePair*, int, int, int, double*,
                                          double*, bool, bool, int, int, const Tables&);
