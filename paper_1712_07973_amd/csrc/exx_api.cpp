@@ -119,7 +119,7 @@ void default_tuning(exx_plan* p) {
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
   p->tuning.zblock_a = 16;
   p->tuning.zblock_c = 8;
-  p->tuning.slab_threads = 256;
+  p->tuning.slab_threads = (p->n == 64 && is_fp32(p)) ? 512 : 256;
 }
 
 void build_schedule(const exx_plan* p, int N, Schedule& s) {
@@ -256,16 +256,24 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
         const auto& sg = s.segments[g];
         EXX_PROF(EXX_PASS_C);
         EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0, c.s0,
-                                 kpsi, e_part, want_k, want_e, p->tuning.zblock_c, s.tile, p->tables));
+                                 kpsi, e_part, want_k, want_e, pair_e != nullptr,
+                                 p->tuning.zblock_c, s.tile, p->tables));
       }
     }
   }
   if (want_e) {
     EXX_PROF(EXX_PASS_FINALIZE);
-    const int count = parseval ? p->ncls * p->n : p->n * p->n / 16;
-    EXX_HIP(launch_slot_reduce(e_part, kparts, count, 2 * (int)s.slots.size(), e_slot, st));
-    EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, parseval,
-                            (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
+    double* eo = (mode & EXX_MODE_ENERGY) ? ex_out : nullptr;
+    if (parseval) {  // one partial per (slot, slab)
+      EXX_HIP(launch_slot_reduce(e_part, kparts, p->ncls * p->n, 2 * (int)s.slots.size(), e_slot, st));
+      EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, 1, eo, nullptr, st));
+    } else if (pair_e) {  // one partial per (slot half, row block)
+      EXX_HIP(launch_slot_reduce(e_part, kparts, p->n * p->n / 16, 2 * (int)s.slots.size(), e_slot, st));
+      EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, 0, eo, pair_e, st));
+    } else {  // one weighted partial per (tile pair, row block)
+      EXX_HIP(launch_slot_reduce(e_part, kparts, p->n * p->n / 16, (int)s.tiles.size(), e_slot, st));
+      EXX_HIP(launch_finalize(s.d_slots, (int)s.tiles.size(), occ, e_slot, N, p->h3, 2, eo, nullptr, st));
+    }
   }
   return EXX_OK;
 }
@@ -309,7 +317,7 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   }
   if (want_e) {
     EXX_PROF(EXX_PASS_FINALIZE);
-    EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, false,
+    EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, 0,
                             (mode & EXX_MODE_ENERGY) ? ex_out : nullptr, pair_e, st));
   }
   return EXX_OK;

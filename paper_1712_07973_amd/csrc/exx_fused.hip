@@ -101,20 +101,20 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
   }
+  const bool ha = sl.ia >= 0, hb = sl.ib >= 0;  // either half may be empty
   T wa = T(1), wb = T(1);
   if (W) {
-    wa = sqrt_weight<T>(occ, sl.ia, sl.ja);
-    if (sl.ib >= 0) wb = sqrt_weight<T>(occ, sl.ib, sl.jb);
+    if (ha) wa = sqrt_weight<T>(occ, sl.ia, sl.ja);
+    if (hb) wb = sqrt_weight<T>(occ, sl.ib, sl.jb);
   }
-  const T* pia = psi + (size_t)sl.ia * M3;
-  const T* pja = psi + (size_t)sl.ja * M3;
-  const T* pib = psi + (size_t)(sl.ib >= 0 ? sl.ib : 0) * M3;
-  const T* pjb = psi + (size_t)(sl.ib >= 0 ? sl.jb : 0) * M3;
-  const bool hb = sl.ib >= 0;
+  const T* pia = psi + (size_t)(ha ? sl.ia : 0) * M3;
+  const T* pja = psi + (size_t)(ha ? sl.ja : 0) * M3;
+  const T* pib = psi + (size_t)(hb ? sl.ib : 0) * M3;
+  const T* pjb = psi + (size_t)(hb ? sl.jb : 0) * M3;
   for (int p = tid; p < ZB * N; p += NT) {
     int zi = p / N, x = p % N;
     size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
-    T a = pia[o] * pja[o] * wa;
+    T a = ha ? pia[o] * pja[o] * wa : T(0);
     T b = hb ? pib[o] * pjb[o] * wb : T(0);
     zb[zi * P + x] = {a, b};
   }
@@ -548,28 +548,22 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
 // (y, z0..z0+ZB), then FP64 pair energies h^3 sum rho V (Eq. 5) and the
 // K psi sums (Eq. 3) of the tile's orbitals at the rows' points.
 //
-// Each thread owns L1 fixed grid points (x = t + 16 k1 of one row) and keeps
-// the K psi partial sums of every tile orbital at them in FP64 registers.
-// The tile pairs of one launch share no orbital (round-robin schedule), so
-// the final update of K psi is a plain read-modify-write: no atomics, and the
-// result does not depend on scheduling.  The next slot's spectrum rows are
-// prefetched into registers while the current slot is reduced.
+// Each thread owns L1 fixed grid points (x = t + 16 k1 of one row).  Slots
+// come in tile order (row a, column pair bb) holding the pairs (a, 2bb) and
+// (a, 2bb+1), so the K psi sums of the J-side orbitals sit in FP64 registers
+// at compile-time indices, and the I-side orbital a has one register set that
+// is added into K psi when its row is done.  The tile pairs of one launch
+// share no orbital (round-robin schedule), so every update of K psi is a plain
+// read-modify-write: no atomics, and results do not depend on scheduling.
+// The next slot's spectrum rows and orbital values are prefetched into
+// registers while the current slot is reduced.
+// Energies: with pair_out, one partial per (slot half, block) for the
+// pair-energy matrix; otherwise one weighted partial per block
+// (sum over the block's pairs of w f_i f_j e_ij, w = 2 off the diagonal).
 // ---------------------------------------------------------------------------
 template <int N>
-constexpr int pass_c_tile() {  // K psi register budget: 2*tile*L1 FP64 values per thread
+constexpr int pass_c_tile() {  // K psi register budget: (tile + 1) * L1 FP64 values per thread
   return N / 16 <= 4 ? 8 : 4;
-}
-
-template <int NO, int L1>
-__device__ __forceinline__ void acc_add(double (&acc)[NO][L1], int lo, const double (&v)[L1]) {
-  // lo is uniform across the block, so this is a chain of scalar branches
-#pragma unroll
-  for (int k = 0; k < NO; ++k) {
-    if (k == lo) {
-#pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) acc[k][k1] += v[k1];
-    }
-  }
 }
 
 template <typename T, int N, int NCLS, int ZB, int NT, int TM>
@@ -579,16 +573,17 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
                                                const Slot* __restrict__ slots,
                                                const TilePair* __restrict__ tiles, int t0,
                                                int slot_base, double* __restrict__ kpsi,
-                                               double* __restrict__ e_slot, int want_k,
-                                               int want_e, const cpx<T>* __restrict__ twg,
+                                               double* __restrict__ e_part, int want_k,
+                                               int want_e, int pair_out,
+                                               const cpx<T>* __restrict__ twg,
                                                const cpx<T>* __restrict__ mdg, int kparts) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
   constexpr int NL = NCLS * ZB;
-  constexpr int NO = 2 * TM;                  // orbitals per tile pair (I then J)
+  constexpr int HB = (TM + 1) / 2;            // column pairs per tile row
+  constexpr int MAXS = TM * HB;               // slots per tile pair
   constexpr int NW = NT / 64;
-  constexpr int MAXS = (TM * TM + 1) / 2;     // slots per tile pair
   constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
   static_assert(ZB * L2 == NT, "one point-owner item per thread");
   __shared__ cpx<T> xs[2][NL * P];  // spectrum rows, double buffered
@@ -596,8 +591,10 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
   __shared__ Slot st[MAXS];
-  __shared__ double fo[NO];
+  __shared__ int smap[TM][HB];
+  __shared__ double fI[TM], fJ[TM];
   __shared__ double ered[MAXS][2][NW];
+  __shared__ double etot[NW];
 
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
@@ -612,175 +609,198 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
   }
-  for (int k = tid; k < ns; k += NT) st[k] = slots[tp.s0 + k];
-  for (int k = tid; k < NO; k += NT) {
-    int o = k < TM ? tp.I0 + k : tp.J0 + (k - TM);
-    bool live = k < TM ? k < tp.nI : (!tp.diag && k - TM < tp.nJ);
-    fo[k] = live ? occ[o] : 0.0;
+  for (int k = tid; k < TM * HB; k += NT) smap[k / HB][k % HB] = -1;
+  for (int k = tid; k < TM; k += NT) {
+    fI[k] = k < tp.nI ? occ[tp.I0 + k] : 0.0;
+    fJ[k] = k < tp.nJ ? occ[tp.J0 + k] : 0.0;
   }
-  double acc[NO][L1];
+  __syncthreads();
+  for (int k = tid; k < ns; k += NT) {
+    const Slot sl = slots[tp.s0 + k];
+    st[k] = sl;
+    const int a = (sl.ia >= 0 ? sl.ia : sl.ib) - tp.I0;
+    const int bb = ((sl.ia >= 0 ? sl.ja : sl.jb) - tp.J0) >> 1;
+    smap[a][bb] = k;
+  }
+  double accJ[TM][L1];
 #pragma unroll
-  for (int lo = 0; lo < NO; ++lo)
+  for (int b = 0; b < TM; ++b)
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) acc[lo][k1] = 0.0;
+    for (int k1 = 0; k1 < L1; ++k1) accJ[b][k1] = 0.0;
+  double ew = 0.0;
 
   // spectrum rows of a slot: values p = tid + k NT -> (cx, kx, zi), zi fastest
   cpx<T> pf[PF];
-  auto fetch = [&](int s) {
-    const cpx<T>* Xs = X + (size_t)(s - slot_base) * NCLS * M3;
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      int p = tid + k * NT;
-      if ((NL * N) % NT == 0 || p < NL * N) {
-        int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
-        pf[k] = Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi];
-      }
-    }
-  };
-  // orbital values of a slot at the owned points
-  T ps[4][L1];
-  auto fetch_psi = [&](const Slot& sl) {
-    const int o[4] = {sl.ia, sl.ja, sl.ib >= 0 ? sl.ib : sl.ia, sl.ib >= 0 ? sl.jb : sl.ja};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const T* po = psi + (size_t)o[q] * M3 + row;
-#pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) ps[q][k1] = po[t_own + L2 * k1];
-    }
-  };
-  if (ns > 0) {
-    fetch(tp.s0);
-    fetch_psi(slots[tp.s0]);
-  }
-  __syncthreads();
-  auto loc = [&](int o) { return (o >= tp.I0 && o < tp.I0 + tp.nI) ? o - tp.I0 : TM + (o - tp.J0); };
-
-#pragma unroll 1
-  for (int k = 0; k < ns; ++k) {
-    cpx<T>* xb = xs[k & 1];
+  auto fetch = [&](int k) {
+    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       int p = tid + q * NT;
       if ((NL * N) % NT == 0 || p < NL * N) {
         int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
-        xb[(cx * ZB + zi) * P + kx] = pf[q];
+        pf[q] = Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi];
       }
     }
-    T cur[4][L1];
+  };
+  // orbital values of a slot at the owned points: [0] I side, [1] J of half a,
+  // [2] J of half b (empty halves read orbital I0, unused)
+  T ps[3][L1];
+  auto fetch_psi = [&](const Slot& sl) {
+    const int o[3] = {sl.ia >= 0 ? sl.ia : sl.ib, sl.ia >= 0 ? sl.ja : tp.I0,
+                      sl.ib >= 0 ? sl.jb : tp.I0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 3; ++q) {
+      const T* po = psi + (size_t)o[q] * M3 + row;
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) cur[q][k1] = ps[q][k1];
-    if (k + 1 < ns) {
-      fetch(tp.s0 + k + 1);
-      fetch_psi(st[k + 1]);
+      for (int k1 = 0; k1 < L1; ++k1) ps[q][k1] = po[t_own + L2 * k1];
     }
-    __syncthreads();
-    // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle; xb -> xo
-    constexpr int C2 = NL * L1;
+  };
+  __syncthreads();
+  if (ns > 0) {
+    fetch(0);
+    fetch_psi(st[0]);
+  }
+
+  int k = 0;  // running slot index (uniform)
+#pragma unroll 1
+  for (int a = 0; a < tp.nI; ++a) {
+    double accI[L1];
 #pragma unroll
-    for (int it = tid; it < C2; it += NT) {
-      int line = it % NL, q1 = it / NL;
-      cpx<T> w[L2];
+    for (int k1 = 0; k1 < L1; ++k1) accI[k1] = 0.0;
+    const double fa = fI[a];
 #pragma unroll
-      for (int q2 = 0; q2 < L2; ++q2) w[q2] = xb[line * P + q1 + L1 * q2];
-      Dft<L2, 1, T>::run(w);
+    for (int bb = 0; bb < HB; ++bb) {
+      if (smap[a][bb] < 0) continue;
+      cpx<T>* xb = xs[k & 1];
 #pragma unroll
-      for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q1]);
+      for (int q = 0; q < PF; ++q) {
+        int p = tid + q * NT;
+        if ((NL * N) % NT == 0 || p < NL * N) {
+          int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
+          xb[(cx * ZB + zi) * P + kx] = pf[q];
+        }
+      }
+      T cur[3][L1];
 #pragma unroll
-      for (int t = 0; t < L2; ++t) xo[line * P + t + L2 * q1] = w[t];
-    }
-    __syncthreads();
-    // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b
-    cpx<T> V[L1];
-    {
-      cpx<T> v[L1];
+      for (int q = 0; q < 3; ++q)
 #pragma unroll
-      for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
-      Dft<L1, 1, T>::run(v);
+        for (int k1 = 0; k1 < L1; ++k1) cur[q][k1] = ps[q][k1];
+      const Slot sl = st[k];
+      if (k + 1 < ns) {
+        fetch(k + 1);
+        fetch_psi(st[k + 1]);
+      }
+      __syncthreads();
+      // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle; xb -> xo
+      constexpr int C2 = NL * L1;
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) V[k1] = v[k1];
-      if (NCLS == 2) {
+      for (int it = tid; it < C2; it += NT) {
+        int line = it % NL, q1 = it / NL;
+        cpx<T> w[L2];
 #pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
+        for (int q2 = 0; q2 < L2; ++q2) w[q2] = xb[line * P + q1 + L1 * q2];
+        Dft<L2, 1, T>::run(w);
+#pragma unroll
+        for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q1]);
+#pragma unroll
+        for (int t = 0; t < L2; ++t) xo[line * P + t + L2 * q1] = w[t];
+      }
+      __syncthreads();
+      // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b
+      cpx<T> V[L1];
+      {
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
         Dft<L1, 1, T>::run(v);
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
-      }
-    }
-    // reductions at the owned points (slot data uniform across the block)
-    const Slot sl = st[k];
-    const bool hb = sl.ib >= 0;
-    const int la_i = loc(sl.ia), la_j = loc(sl.ja);
-    double ea = 0.0, eb = 0.0;
-    {
-      double vi[L1], vj[L1];
-      const double fi = fo[la_i], fj = fo[la_j];
+        for (int k1 = 0; k1 < L1; ++k1) V[k1] = v[k1];
+        if (NCLS == 2) {
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) {
-        const T a = cur[0][k1], b = cur[1][k1];
-        const double Va = (double)V[k1].x;
-        ea += (double)(a * b) * Va;
-        vi[k1] = fj * Va * (double)b;  // into (K psi)_ia
-        vj[k1] = fi * Va * (double)a;  // into (K psi)_ja
-      }
-      if (want_k) {
-        acc_add<NO, L1>(acc, la_i, vi);
-        if (sl.ia != sl.ja) acc_add<NO, L1>(acc, la_j, vj);
-      }
-    }
-    if (hb) {
-      const int lb_i = loc(sl.ib), lb_j = loc(sl.jb);
-      double vi[L1], vj[L1];
-      const double fi = fo[lb_i], fj = fo[lb_j];
+          for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
+          Dft<L1, 1, T>::run(v);
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) {
-        const T a = cur[2][k1], b = cur[3][k1];
-        const double Vb = (double)V[k1].y;
-        eb += (double)(a * b) * Vb;
-        vi[k1] = fj * Vb * (double)b;
-        vj[k1] = fi * Vb * (double)a;
+          for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
+        }
       }
-      if (want_k) {
-        acc_add<NO, L1>(acc, lb_i, vi);
-        if (sl.ib != sl.jb) acc_add<NO, L1>(acc, lb_j, vj);
-      }
-    }
-    if (want_e) {
+      // the two halves: J columns 2bb and 2bb + 1 (compile-time register indices)
+      double eh[2] = {0.0, 0.0};
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        ea += __shfl_xor(ea, off);
-        eb += __shfl_xor(eb, off);
+      for (int h = 0; h < 2; ++h) {
+        const int b = 2 * bb + h;
+        if (b >= TM) continue;
+        const bool valid = h ? sl.ib >= 0 : sl.ia >= 0;
+        if (!valid) continue;
+        const bool self = tp.diag && b == a;  // the (a, a) pair updates (K psi)_a once
+        const double fb = fJ[b];
+        double e = 0.0;
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) {
+          const T pa = cur[0][k1], pb = cur[1 + h][k1];
+          const double Vv = (double)(h ? V[k1].y : V[k1].x);
+          e += (double)(pa * pb) * Vv;
+          if (want_k) {
+            accI[k1] += fb * Vv * (double)pb;
+            if (!self) accJ[b][k1] += fa * Vv * (double)pa;
+          }
+        }
+        eh[h] = e;
+        if (!pair_out) ew += (self ? 1.0 : 2.0) * fa * fb * e;
       }
-      if ((tid & 63) == 0) {
-        ered[k][0][tid >> 6] = ea;
-        ered[k][1][tid >> 6] = eb;
+      if (want_e && pair_out) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          eh[0] += __shfl_xor(eh[0], off);
+          eh[1] += __shfl_xor(eh[1], off);
+        }
+        if ((tid & 63) == 0) {
+          ered[k][0][tid >> 6] = eh[0];
+          ered[k][1][tid >> 6] = eh[1];
+        }
       }
+      ++k;
+    }
+    if (want_k) {
+      double* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += accI[k1];
     }
   }
-  __syncthreads();
-  if (want_e) {
+  if (want_k) {
+    // J-side sums; a diagonal tile adds them to orbitals whose row sums are in
+    // already (same block, program order)
+#pragma unroll
+    for (int b = 0; b < TM; ++b) {
+      if (b >= tp.nJ) continue;
+      double* ko = kpsi + (size_t)(tp.J0 + b) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += accJ[b][k1];
+    }
+  }
+  if (!want_e) return;
+  if (pair_out) {
+    __syncthreads();
     // one partial per (slot half, row block), summed in a fixed order later
     for (int q = tid; q < 2 * ns; q += NT) {
-      const int k = q >> 1, half = q & 1;
+      const int kk = q >> 1, half = q & 1;
       double sum = 0.0;
-      if (!(half && st[k].ib < 0)) {
+      if (half ? st[kk].ib >= 0 : st[kk].ia >= 0) {
 #pragma unroll
-        for (int w2 = 0; w2 < NW; ++w2) sum += ered[k][half][w2];
+        for (int w2 = 0; w2 < NW; ++w2) sum += ered[kk][half][w2];
       }
-      e_slot[(size_t)(2 * (tp.s0 + k) + half) * kparts + blockIdx.x] = sum;
+      e_part[(size_t)(2 * (tp.s0 + kk) + half) * kparts + blockIdx.x] = sum;
     }
-  }
-  if (!want_k) return;
-  // K psi += partial sums; the launch's tile pairs are orbital-disjoint
+  } else {
 #pragma unroll
-  for (int lo = 0; lo < NO; ++lo) {
-    const bool live = lo < TM ? (lo < tp.nI) : (!tp.diag && lo - TM < tp.nJ);
-    if (!live) continue;
-    const int o = lo < TM ? tp.I0 + lo : tp.J0 + (lo - TM);
-    double* ko = kpsi + (size_t)o * M3 + row;
+    for (int off = 32; off > 0; off >>= 1) ew += __shfl_xor(ew, off);
+    if ((tid & 63) == 0) etot[tid >> 6] = ew;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += acc[lo][k1];
+      for (int w2 = 0; w2 < NW; ++w2) sum += etot[w2];
+      e_part[(size_t)(t0 + blockIdx.y) * kparts + blockIdx.x] = sum;
+    }
   }
 }
 
@@ -817,21 +837,28 @@ hipError_t launch_slot_reduce(const double* parts, int kparts, int count, int nh
 // ---------------------------------------------------------------------------
 // finalize: E_x = -1/2 sum_ij f_i f_j e_ij in a fixed order, pair-energy matrix
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_finalize(const Slot* __restrict__ slots, int nslots,
+// sum_mode 0: per-pair energies e_slot[2s + h] (weights f_i f_j, 2 off the
+// diagonal; pair-energy matrix written if requested); 1: Parseval sums of
+// weighted slots e_slot[2s]; 2: nvals weighted partial sums e_slot[0..nvals).
+__global__ __launch_bounds__(1024) void k_finalize(const Slot* __restrict__ slots, int nvals,
                                                    const double* __restrict__ occ,
                                                    const double* __restrict__ e_slot, int n_orb,
-                                                   double h3, int packed_energy,
+                                                   double h3, int sum_mode,
                                                    double* __restrict__ ex_out,
                                                    double* __restrict__ pair_e) {
   __shared__ double red[16];
   const int tid = threadIdx.x;
   double sum = 0.0;
-  for (int s = tid; s < nslots; s += 1024) {
-    const Slot sl = slots[s];
-    if (packed_energy) {
+  for (int s = tid; s < nvals; s += 1024) {
+    if (sum_mode == 2) {
+      sum += h3 * e_slot[s];
+      continue;
+    }
+    if (sum_mode == 1) {
       sum += h3 * e_slot[2 * s];
       continue;
     }
+    const Slot sl = slots[s];
     for (int half = 0; half < 2; ++half) {
       int i = half ? sl.ib : sl.ia, j = half ? sl.jb : sl.ja;
       if (i < 0) continue;
@@ -854,11 +881,11 @@ __global__ __launch_bounds__(1024) void k_finalize(const Slot* __restrict__ slot
   }
 }
 
-hipError_t launch_finalize(const Slot* slots, int nslots, const double* occ, const double* e_slot,
-                           int n_orb, double h3, bool packed_energy, double* ex_out,
-                           double* pair_e, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, slots, nslots, occ, e_slot, n_orb, h3,
-                     packed_energy ? 1 : 0, ex_out, pair_e);
+hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, const double* e_slot,
+                           int n_orb, double h3, int sum_mode, double* ex_out, double* pair_e,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, slots, nvals, occ, e_slot, n_orb, h3,
+                     sum_mode, ex_out, pair_e);
   return hipGetLastError();
 }
 
@@ -995,7 +1022,7 @@ template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
-                         int zb, int tmax, const Tables& tb) {
+                         bool pair_out, int zb, int tmax, const Tables& tb) {
   if (ntiles <= 0) return hipSuccess;
   (void)zb;
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
@@ -1013,11 +1040,11 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
       if (L.ncls == 2)
         hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                           want_e ? 1 : 0, tw, md, energy_parts(N));
+                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
       else
         hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                           want_e ? 1 : 0, tw, md, energy_parts(N));
+                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
       return hipGetLastError();
     }
   });
@@ -1033,10 +1060,10 @@ template hipError_t launch_pass_b<double>(const Launch&, void*, int, bool, doubl
                                           const Tables&, int);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
                                          const Slot*, const TilePair*, int, int, int, double*,
-                                         double*, bool, bool, int, int, const Tables&);
+                                         double*, bool, bool, bool, int, int, const Tables&);
 template hipError_t launch_pass_c<double>(const Launch&, const void*, const double*,
                                           const double*, const Slot*, const TilePair*, int, int,
-                                          int, double*, double*, bool, bool, int, int,
+                                          int, double*, double*, bool, bool, bool, int, int,
                                           const Tables&);
 
 }  // namespace exx

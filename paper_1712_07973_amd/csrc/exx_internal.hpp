@@ -68,13 +68,13 @@ template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
-                         int zb, int tmax, const Tables& tb);
+                         bool pair_out, int zb, int tmax, const Tables& tb);
 int energy_parts(int n);  // pair-energy partials per slot half (fused passes)
 hipError_t launch_slot_reduce(const double* parts, int kparts, int count, int nhalves,
                               double* e_slot, hipStream_t s);
-hipError_t launch_finalize(const Slot* slots, int nslots, const double* occ, const double* e_slot,
-                           int n_orb, double h3, bool packed_energy, double* ex_out,
-                           double* pair_e, hipStream_t s);
+hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, const double* e_slot,
+                           int n_orb, double h3, int sum_mode, double* ex_out, double* pair_e,
+                           hipStream_t s);
 
 bool fused_supported(int precision, int n);
 int pass_c_max_tile(int n);  // largest pair-tile edge pass C supports at grid n

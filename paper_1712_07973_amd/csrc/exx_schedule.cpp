@@ -61,26 +61,29 @@ void build_schedule_host(int N, int T, int batch_slots, bool packed, Schedule& s
       tp.J0 = J * T;
       tp.nJ = std::min(T, N - tp.J0);
       tp.diag = (I == J);
-      std::vector<std::pair<int, int>> pairs;
-      for (int a = 0; a < tp.nI; ++a)
-        for (int b = tp.diag ? a : 0; b < tp.nJ; ++b) pairs.push_back({tp.I0 + a, tp.J0 + b});
+      // slot (a, bb) holds the pairs (I0 + a, J0 + 2bb) and (I0 + a, J0 + 2bb + 1);
+      // a half outside the tile (ragged edge) or below the diagonal is empty
+      // (orbital index -1).  Fully empty slots are not emitted.
       tp.s0 = (int)s.slots.size();
-      for (size_t k = 0; k < pairs.size(); k += 2) {
-        Slot sl{pairs[k].first, pairs[k].second, -1, -1};
-        if (k + 1 < pairs.size()) {
-          sl.ib = pairs[k + 1].first;
-          sl.jb = pairs[k + 1].second;
+      for (int a = 0; a < tp.nI; ++a)
+        for (int bb = 0; 2 * bb < tp.nJ; ++bb) {
+          Slot sl{-1, -1, -1, -1};
+          for (int h = 0; h < 2; ++h) {
+            const int b = 2 * bb + h;
+            const bool ok = b < tp.nJ && (!tp.diag || b >= a);
+            if (!ok) continue;
+            (h ? sl.ib : sl.ia) = tp.I0 + a;
+            (h ? sl.jb : sl.ja) = tp.J0 + b;
+          }
+          if (sl.ia >= 0 || sl.ib >= 0) s.slots.push_back(sl);
         }
-        s.slots.push_back(sl);
-      }
       tp.s1 = (int)s.slots.size();
       s.tiles.push_back(tp);
       round_of.push_back((int)r);
     }
   // chunks of whole tile pairs whose slots fit the launch capacity; pass C
   // segments split chunks at round boundaries
-  const int maxtp = (T * (T + 1)) / 2;
-  const int cap = std::max(batch_slots, (maxtp + 1) / 2);
+  const int cap = std::max(batch_slots, T * ((T + 1) / 2));
   int t0 = 0;
   while (t0 < (int)s.tiles.size()) {
     int t1 = t0;

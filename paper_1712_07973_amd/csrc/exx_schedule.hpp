@@ -7,8 +7,9 @@
 namespace exx {
 
 // One packed slot = two unordered pairs (ia, ja) and (ib, jb) sharing one
-// complex transform (real part: pair a, imaginary part: pair b); ib < 0 marks
-// an empty second half.  Slots are grouped by pair tile.
+// complex transform (real part: pair a, imaginary part: pair b); a negative
+// orbital index marks an empty half.  Within a pair tile the slot of row a and
+// column pair bb holds (I0 + a, J0 + 2bb) and (I0 + a, J0 + 2bb + 1).
 struct Slot {
   int ia, ja, ib, jb;
 };

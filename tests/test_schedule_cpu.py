@@ -51,20 +51,32 @@ def test_packed_schedule_invariants(probe, N, T, cap):
     assert head[0] == N * (N + 1) // 2
     pairs = []
     for ia, ja, ib, jb in r["S"]:
-        pairs.append((ia, ja))
+        if ia >= 0:
+            pairs.append((ia, ja))
         if ib >= 0:
             pairs.append((ib, jb))
     assert sorted(pairs) == [(i, j) for i in range(N) for j in range(i, N)]
-    # slots of a tile pair belong to it; at most one half-empty slot per tile pair
+    # slots of a tile pair belong to it and follow the (row a, column pair bb)
+    # layout: halves (I0+a, J0+2bb) and (I0+a, J0+2bb+1), rows in order
     for s0, s1, I0, nI, J0, nJ, diag in r["T"]:
-        half = 0
+        prev = (-1, -1)
         for ia, ja, ib, jb in r["S"][s0:s1]:
-            for i, j in ((ia, ja), (ib, jb)):
-                if i < 0:
-                    half += 1
-                    continue
-                assert I0 <= i < I0 + nI and J0 <= j < J0 + nJ
-        assert half <= 1
+            assert ia >= 0 or ib >= 0
+            a = (ia if ia >= 0 else ib) - I0
+            bb = ((ja if ia >= 0 else jb) - J0) // 2
+            assert (a, bb) > prev
+            prev = (a, bb)
+            for h, (i, j) in enumerate(((ia, ja), (ib, jb))):
+                b = 2 * bb + h
+                valid = b < nJ and (not diag or b >= a)
+                assert (i >= 0) == valid
+                if valid:
+                    assert (i, j) == (I0 + a, J0 + b)
+    # when T is even and tiles are full, off-diagonal slots are never half empty
+    if N % T == 0 and T % 2 == 0:
+        for s0, s1, I0, nI, J0, nJ, diag in r["T"]:
+            if not diag:
+                assert all(x[0] >= 0 and x[2] >= 0 for x in r["S"][s0:s1])
     # segments are orbital-disjoint
     for t0, t1 in r["G"]:
         seen = set()
@@ -76,7 +88,7 @@ def test_packed_schedule_invariants(probe, N, T, cap):
     s_prev, t_prev = 0, 0
     for t0, t1, s0, s1, g0, g1 in r["C"]:
         assert t0 == t_prev and s0 == s_prev
-        assert s1 - s0 <= max(cap, (T * (T + 1) // 2 + 1) // 2)
+        assert s1 - s0 <= max(cap, T * ((T + 1) // 2))
         assert r["G"][g0][0] == t0 and r["G"][g1 - 1][1] == t1
         t_prev, s_prev = t1, s1
     assert s_prev == len(r["S"]) and t_prev == len(r["T"])
