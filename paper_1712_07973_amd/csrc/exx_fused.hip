@@ -270,11 +270,17 @@ struct SlabFft {
         Dft<L2, -1, T>::run(v);
         const int kyf = PAD ? 2 * ky + cy : ky;
         const T* kr = kt + (size_t)fold(kyf, M) * H;
+        // kz = q1 + L1 q2 and its kernel index kzf = c + step q2 (c = 2 q1 + cz
+        // padded, q1 periodic): below half the range fold(kzf) = kzf, above it
+        // M - kzf, with the switch exactly at q2 = L2 / 2, so both halves are a
+        // base pointer plus compile-time offsets.
+        constexpr int step = PAD ? 2 * L1 : L1;
+        const int c = PAD ? 2 * q1 + cz : q1;
+        const T* k_lo = kr + c;
+        const T* k_hi = kr + (M - c);
 #pragma unroll
         for (int q2 = 0; q2 < L2; ++q2) {
-          int kz = q1 + L1 * q2;
-          int kzf = PAD ? 2 * kz + cz : kz;
-          T kv = kr[fold(kzf, M)];
+          T kv = (2 * q2 < L2) ? k_lo[step * q2] : k_hi[-step * q2];
           if (EONLY) {
             esum += (double)kv *
                     ((double)v[q2].x * (double)v[q2].x + (double)v[q2].y * (double)v[q2].y);
@@ -566,8 +572,15 @@ constexpr int pass_c_tile() {  // K psi register budget: (tile + 1) * L1 FP64 va
   return N / 16 <= 4 ? 8 : 4;
 }
 
+// FP32 at n <= 32: ask for 3 waves per SIMD (168 registers); larger grids
+// need more registers for the per-thread points
+template <typename T, int N>
+constexpr int pass_c_min_waves() {
+  return (sizeof(T) == 4 && N <= 32) ? 3 : 1;
+}
+
 template <typename T, int N, int NCLS, int ZB, int NT, int TM>
-__global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
+__global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const cpx<T>* __restrict__ X,
                                                const T* __restrict__ psi,
                                                const double* __restrict__ occ,
                                                const Slot* __restrict__ slots,
@@ -586,7 +599,9 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   constexpr int NW = NT / 64;
   constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
   static_assert(ZB * L2 == NT, "one point-owner item per thread");
-  __shared__ cpx<T> xs[2][NL * P];  // spectrum rows, double buffered
+  // Spectrum rows of the current slot.  One buffer suffices: the store of
+  // slot k+1 follows the second barrier of slot k, after every read of xs.
+  __shared__ cpx<T> xs[NL * P];
   __shared__ cpx<T> xo[NL * P];     // after the inverse step 2
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
@@ -595,6 +610,7 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
   __shared__ double fI[TM], fJ[TM];
   __shared__ double ered[MAXS][2][NW];
   __shared__ double etot[NW];
+  __shared__ T pJs[TM][L1 * NT];
 
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
@@ -642,36 +658,37 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
       }
     }
   };
-  // orbital values of a slot at the owned points: [0] I side, [1] J of half a,
-  // [2] J of half b (empty halves read orbital I0, unused)
-  T ps[3][L1];
-  auto fetch_psi = [&](const Slot& sl) {
-    const int o[3] = {sl.ia >= 0 ? sl.ia : sl.ib, sl.ia >= 0 ? sl.ja : tp.I0,
-                      sl.ib >= 0 ? sl.jb : tp.I0};
+  // orbital values at the owned points: every J-side orbital of the tile once
+  // into LDS (slot [b][k1 NT + tid], read back by the same thread only), the
+  // I-side orbital once per row into registers
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T* po = psi + (size_t)o[q] * M3 + row;
+  for (int b = 0; b < TM; ++b) {
+    if (b >= tp.nJ) continue;
+    const T* po = psi + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) ps[q][k1] = po[t_own + L2 * k1];
-    }
-  };
-  __syncthreads();
-  if (ns > 0) {
-    fetch(0);
-    fetch_psi(st[0]);
+    for (int k1 = 0; k1 < L1; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * k1];
   }
+  __syncthreads();
+  if (ns > 0) fetch(0);
 
   int k = 0;  // running slot index (uniform)
 #pragma unroll 1
   for (int a = 0; a < tp.nI; ++a) {
     double accI[L1];
+    T pI[L1];
+    {
+      const T* po = psi + (size_t)(tp.I0 + a) * M3 + row;
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) accI[k1] = 0.0;
+      for (int k1 = 0; k1 < L1; ++k1) {
+        accI[k1] = 0.0;
+        pI[k1] = po[t_own + L2 * k1];
+      }
+    }
     const double fa = fI[a];
 #pragma unroll
     for (int bb = 0; bb < HB; ++bb) {
       if (smap[a][bb] < 0) continue;
-      cpx<T>* xb = xs[k & 1];
+      cpx<T>* xb = xs;
 #pragma unroll
       for (int q = 0; q < PF; ++q) {
         int p = tid + q * NT;
@@ -680,16 +697,8 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
           xb[(cx * ZB + zi) * P + kx] = pf[q];
         }
       }
-      T cur[3][L1];
-#pragma unroll
-      for (int q = 0; q < 3; ++q)
-#pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) cur[q][k1] = ps[q][k1];
       const Slot sl = st[k];
-      if (k + 1 < ns) {
-        fetch(k + 1);
-        fetch_psi(st[k + 1]);
-      }
+      if (k + 1 < ns) fetch(k + 1);  // spectrum rows of the next slot
       __syncthreads();
       // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle; xb -> xo
       constexpr int C2 = NL * L1;
@@ -736,7 +745,7 @@ __global__ __launch_bounds__(NT) void k_pass_c(const cpx<T>* __restrict__ X,
         double e = 0.0;
 #pragma unroll
         for (int k1 = 0; k1 < L1; ++k1) {
-          const T pa = cur[0][k1], pb = cur[1 + h][k1];
+          const T pa = pI[k1], pb = pJs[b][k1 * NT + tid];
           const double Vv = (double)(h ? V[k1].y : V[k1].x);
           e += (double)(pa * pb) * Vv;
           if (want_k) {

@@ -13,7 +13,6 @@ from __future__ import annotations
 
 import csv
 import glob
-import hashlib
 import json
 import os
 import sys
@@ -42,12 +41,13 @@ def main(argv) -> int:
     copy_f = counter_per_dispatch(fc, "FETCH_SIZE", "copy") * 1024
     copy_w = counter_per_dispatch(wc, "WRITE_SIZE", "copy") * 1024
     kf, kw = COPY_BYTES / copy_f, COPY_BYTES / copy_w
-    src = os.path.join(ROOT, "paper_1712_07973_amd", "csrc", "exx_fused.hip")
+    sys.path.insert(0, ROOT)
+    from bench import kernel_source_sha1
     out = {"kernel": kernel, "workload": workload,
            "fetch_bytes_per_dispatch_raw": fetch, "write_bytes_per_dispatch_raw": write,
            "copy_probe_fetch_factor": kf, "copy_probe_write_factor": kw,
            "hbm_bytes_per_launch": int(fetch * kf + write * kw),
-           "source_sha1": hashlib.sha1(open(src, "rb").read()).hexdigest()}
+           "source_sha1": kernel_source_sha1(kernel)}
     base = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic")
     with open(base + ".json", "w") as f:
         json.dump(out, f, indent=1)
