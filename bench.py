@@ -75,13 +75,14 @@ PASS_SECTIONS = {"pass_a": ("// pass A:", "// pass B:"), "pass_b": ("// pass B:"
 
 
 def kernel_source_sha1(kernel: str) -> str:
-    """SHA-1 of the kernel's section of exx_fused.hip plus the DFT header."""
+    """SHA-1 of the kernel's section of exx_fused.hip, the helpers ahead of
+    pass A (spectrum layout, shared device functions) and the DFT header."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1712_07973_amd", "csrc")
     with open(os.path.join(csrc, "exx_fused.hip")) as f:
         text = f.read()
     a, b = PASS_SECTIONS[kernel]
-    section = text[text.index(a):text.index(b)]
+    section = text[:text.index(PASS_SECTIONS["pass_a"][0])] + text[text.index(a):text.index(b)]
     with open(os.path.join(csrc, "exx_fft.hpp")) as f:
         section += f.read()
     return hashlib.sha1(section.encode()).hexdigest()
@@ -197,6 +198,10 @@ def main(argv=None) -> int:
     ap.add_argument("--slab-threads", type=int, default=0,
                     help="threads per slab workgroup of the y/z pass (0: plan default)")
     ap.add_argument("--tile", type=int, default=0, help="pair-tile edge (0: plan default)")
+    ap.add_argument("--batch-slots", type=int, default=0,
+                    help="slots per launch chunk (0: plan default)")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="1: serial passes, 3: overlapped rounds (0: plan default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates memory counters)")
     a = ap.parse_args(argv)
@@ -238,7 +243,8 @@ def main(argv=None) -> int:
     ex = torch.empty((), dtype=torch.float64, device=dev)
 
     plan = exx.Plan(grid, "fp32", n_orb_max=N)
-    plan.set_tuning(tile=a.tile, slab_threads=a.slab_threads)
+    plan.set_tuning(tile=a.tile, slab_threads=a.slab_threads, batch_slots=a.batch_slots,
+                    streams=a.streams)
     plan.workspace(N)
     _, n_slots = plan.schedule_info(N)
     ms, wall, prof = timed(plan, psi, occ, kpsi, ex, a.steps, a.warmup)

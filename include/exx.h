@@ -128,14 +128,18 @@ int exx_compute(exx_plan* plan, const double* psi, const double* occ, int n_orb,
                 unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
                 size_t ws_bytes, void* stream);
 
-/* Tuning knobs of a plan (pair-tile edge, slots per launch, rows per
- * workgroup).  Returned by exx_autotune and settable explicitly; 0 = keep. */
+/* Tuning knobs of a plan (pair-tile edge, slots per launch, slab workgroup
+ * size, pass streams).  Returned by exx_autotune and settable explicitly;
+ * a field left 0 keeps the plan's value.  Every setting gives the same
+ * results bit for bit except `tile`, which changes the summation order. */
 typedef struct exx_tuning {
-  int tile;        /* orbitals per pair-tile edge (2..16) */
-  int batch_slots; /* packed pair slots per pass launch (>= 1) */
-  int zblock_a;    /* grid rows per workgroup in the pair-build / forward pass */
-  int zblock_c;    /* grid rows per workgroup in the inverse / reduction pass */
+  int tile;         /* orbitals per pair-tile edge (2..16) */
+  int batch_slots;  /* packed pair slots per pass launch (>= 1) */
   int slab_threads; /* threads per slab workgroup of the y/z pass (256 or 512 at n = 64) */
+  int streams;      /* 1: every pass on the caller's stream, one launch per pass and chunk;
+                       3: per round of pair tiles, the pair-build pass, the y/z pass and the
+                       reduction pass run on three streams, so that the memory-bound passes
+                       of one round overlap the y/z pass of another (fused paths only) */
 } exx_tuning;
 
 int exx_plan_get_tuning(const exx_plan* plan, exx_tuning* out);

@@ -5,9 +5,10 @@ differentiable E_x (autograd backward = recomputed K psi); ``Plan`` exposes
 the C ABI (precisions 'fp32', 'fp64_plain', 'fp64_fused', tuning, autotune);
 ``Batch`` evaluates many independent systems in one captured HIP graph.
 """
+from ._lib import ExxError
 from .api import Grid, Plan, energy_and_kpsi, get_plan, library_version
 from .autograd import ExchangeEnergy, exchange_energy
 from .batch import Batch
 
 __all__ = ["Grid", "Plan", "Batch", "energy_and_kpsi", "exchange_energy", "ExchangeEnergy",
-           "get_plan", "library_version"]
+           "ExxError", "get_plan", "library_version"]

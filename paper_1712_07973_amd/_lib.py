@@ -32,8 +32,8 @@ class ExxGrid(C.Structure):
 
 
 class ExxTuning(C.Structure):
-    _fields_ = [("tile", C.c_int), ("batch_slots", C.c_int), ("zblock_a", C.c_int),
-                ("zblock_c", C.c_int), ("slab_threads", C.c_int)]
+    _fields_ = [("tile", C.c_int), ("batch_slots", C.c_int), ("slab_threads", C.c_int),
+                ("streams", C.c_int)]
 
 
 PASS_KINDS = ["convert", "zero", "pass_a", "pass_b", "pass_c", "finalize", "plain_fft",

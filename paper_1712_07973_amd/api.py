@@ -129,13 +129,13 @@ class Plan:
     def tuning(self) -> dict:
         t = L.ExxTuning()
         L.check(L.lib().exx_plan_get_tuning(self._h, C.byref(t)), "exx_plan_get_tuning")
-        return {"tile": t.tile, "batch_slots": t.batch_slots, "zblock_a": t.zblock_a,
-                "zblock_c": t.zblock_c, "slab_threads": t.slab_threads}
+        return {"tile": t.tile, "batch_slots": t.batch_slots, "slab_threads": t.slab_threads,
+                "streams": t.streams}
 
-    def set_tuning(self, tile: int = 0, batch_slots: int = 0, zblock_a: int = 0,
-                   zblock_c: int = 0, slab_threads: int = 0) -> None:
-        t = L.ExxTuning(int(tile), int(batch_slots), int(zblock_a), int(zblock_c),
-                        int(slab_threads))
+    def set_tuning(self, tile: int = 0, batch_slots: int = 0, slab_threads: int = 0,
+                   streams: int = 0) -> None:
+        """0 keeps a field; streams is 1 (serial passes) or 3 (overlapped rounds)."""
+        t = L.ExxTuning(int(tile), int(batch_slots), int(slab_threads), int(streams))
         L.check(L.lib().exx_plan_set_tuning(self._h, C.byref(t)), "exx_plan_set_tuning")
 
     def enable_profiling(self, on: bool = True) -> None:

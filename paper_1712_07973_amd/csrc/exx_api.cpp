@@ -117,9 +117,8 @@ void default_tuning(exx_plan* p) {
   const size_t budget = (size_t)4 << 30;  // bytes of spectrum workspace per launch chunk
   size_t per = slot_bytes(p);
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
-  p->tuning.zblock_a = 16;
-  p->tuning.zblock_c = 8;
   p->tuning.slab_threads = (p->n == 64 && is_fp32(p)) ? 512 : 256;
+  p->tuning.streams = 1;
 }
 
 void build_schedule(const exx_plan* p, int N, Schedule& s) {
@@ -177,6 +176,14 @@ int get_schedule(exx_plan* p, int N, Schedule** out, bool allow_build) {
     EXX_HIP(hipMalloc((void**)&s.d_tiles, s.tiles.size() * sizeof(TilePair)));
     EXX_HIP(hipMemcpy(s.d_tiles, s.tiles.data(), s.tiles.size() * sizeof(TilePair), hipMemcpyHostToDevice));
   }
+  // fork/join events of the overlapped rounds: one fork, then per round one
+  // event after pass A, one after pass B and one after pass C
+  const size_t need = 1 + 3 * s.segments.size();
+  while (p->sync_ev.size() < need) {
+    hipEvent_t e;
+    EXX_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    p->sync_ev.push_back(e);
+  }
   EXX_HIP(hipSetDevice(dev));
   auto res = p->schedules.emplace(N, std::move(s));
   *out = &res.first->second;
@@ -212,6 +219,13 @@ struct Prof {
   }
 };
 #define EXX_PROF(kind) Prof prof_##__LINE__(p, kind, st)
+#define EXX_PROF_ON(kind, stream) Prof prof_##__LINE__(p, kind, stream)
+
+// Slots of one round (segment) of a chunk: its tile pairs' slots are contiguous.
+void segment_slots(const Schedule& s, int g, int* a, int* b) {
+  *a = s.tiles[s.segments[g].t0].s0;
+  *b = s.tiles[s.segments[g].t1 - 1].s1;
+}
 
 template <typename T>
 int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* psi,
@@ -235,31 +249,93 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
   double* e_part = reinterpret_cast<double*>(ws + w.e_part);
   const int kparts = energy_parts(p->n);
-  void* X = ws + w.X;
+  char* X = ws + w.X;
+  const size_t sb = slot_bytes(p);
   {
     EXX_PROF(EXX_PASS_ZERO);
     if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
   }
   Launch L{p->n, p->ncls, p->m, p->h3, st};
-  for (const auto& c : s.chunks) {
-    const int ns = c.s1 - c.s0;
-    {
-      EXX_PROF(EXX_PASS_A);
-      EXX_HIP(launch_pass_a<T>(L, psiT, X, s.d_slots, c.s0, ns, occ, parseval, p->tuning.zblock_a, p->tables));
-    }
-    {
-      EXX_PROF(EXX_PASS_B);
-      EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_part, c.s0, p->tables, p->tuning.slab_threads));
-    }
-    if (!parseval) {
-      for (int g = c.seg0; g < c.seg1; ++g) {
-        const auto& sg = s.segments[g];
-        EXX_PROF(EXX_PASS_C);
-        EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0, c.s0,
-                                 kpsi, e_part, want_k, want_e, pair_e != nullptr,
-                                 p->tuning.zblock_c, s.tile, p->tables));
+  const bool overlap = p->tuning.streams == 3 && p->side[0] && p->side[1] &&
+                       p->sync_ev.size() >= 1 + 3 * s.segments.size();
+  if (!overlap) {
+    for (const auto& c : s.chunks) {
+      const int ns = c.s1 - c.s0;
+      {
+        EXX_PROF(EXX_PASS_A);
+        EXX_HIP(launch_pass_a<T>(L, psiT, X, s.d_slots, c.s0, ns, occ, parseval, p->tables));
+      }
+      {
+        EXX_PROF(EXX_PASS_B);
+        EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_part, c.s0, p->tables, p->tuning.slab_threads));
+      }
+      if (!parseval) {
+        for (int g = c.seg0; g < c.seg1; ++g) {
+          const auto& sg = s.segments[g];
+          EXX_PROF(EXX_PASS_C);
+          EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0, c.s0,
+                                   kpsi, e_part, want_k, want_e, pair_e != nullptr, s.tile,
+                                   p->tables));
+        }
       }
     }
+  } else {
+    // Rounds in a pipeline over three streams: pass A of round g on sa, pass B
+    // on the caller's stream once A(g) is done, pass C on sc once B(g) is done.
+    // Rounds of a chunk own disjoint slots of X, so A(g+1) and C(g-1) may run
+    // beside B(g); the next chunk's pass A reuses X only after the previous
+    // chunk's last reader of X is done (its last pass C, or its last pass B in
+    // the energy-only mode, which has no pass C).  Pass C launches stay in
+    // round order on sc, so the K psi updates keep the order of the serial path.
+    hipStream_t sa = p->side[0], sc = p->side[1];
+    Launch La = L, Lc = L;
+    La.stream = sa;
+    Lc.stream = sc;
+    size_t ev = 0;
+    hipEvent_t fork = p->sync_ev[ev++];
+    EXX_HIP(hipEventRecord(fork, st));
+    EXX_HIP(hipStreamWaitEvent(sa, fork, 0));
+    if (!parseval) EXX_HIP(hipStreamWaitEvent(sc, fork, 0));
+    hipEvent_t last_c = nullptr, last_use = nullptr;
+    for (const auto& c : s.chunks) {
+      if (last_use) EXX_HIP(hipStreamWaitEvent(sa, last_use, 0));
+      for (int g = c.seg0; g < c.seg1; ++g) {
+        int a0, a1;
+        segment_slots(s, g, &a0, &a1);
+        char* Xg = X + (size_t)(a0 - c.s0) * sb;
+        {
+          EXX_PROF_ON(EXX_PASS_A, sa);
+          EXX_HIP(launch_pass_a<T>(La, psiT, Xg, s.d_slots, a0, a1 - a0, occ, parseval, p->tables));
+        }
+        hipEvent_t ea = p->sync_ev[ev++];
+        EXX_HIP(hipEventRecord(ea, sa));
+        EXX_HIP(hipStreamWaitEvent(st, ea, 0));
+        {
+          EXX_PROF(EXX_PASS_B);
+          EXX_HIP(launch_pass_b<T>(L, Xg, a1 - a0, parseval, e_part, a0, p->tables,
+                                   p->tuning.slab_threads));
+        }
+        hipEvent_t eb = p->sync_ev[ev++];
+        EXX_HIP(hipEventRecord(eb, st));
+        if (parseval) {
+          last_use = eb;
+          continue;
+        }
+        EXX_HIP(hipStreamWaitEvent(sc, eb, 0));
+        {
+          const auto& sg = s.segments[g];
+          EXX_PROF_ON(EXX_PASS_C, sc);
+          EXX_HIP(launch_pass_c<T>(Lc, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0,
+                                   c.s0, kpsi, e_part, want_k, want_e, pair_e != nullptr, s.tile,
+                                   p->tables));
+        }
+        last_c = p->sync_ev[ev++];
+        EXX_HIP(hipEventRecord(last_c, sc));
+        last_use = last_c;
+      }
+    }
+    // sa's last pass A is already joined by the pass B that waited for it
+    if (last_c) EXX_HIP(hipStreamWaitEvent(st, last_c, 0));
   }
   if (want_e) {
     EXX_PROF(EXX_PASS_FINALIZE);
@@ -391,6 +467,15 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
     delete p;
     return hip_fail(e, "hipGetDevice");
   }
+  if (!is_plain(p)) {
+    for (auto& q : p->side) {
+      e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+      if (e != hipSuccess) {
+        exx_plan_destroy(p);
+        return hip_fail(e, "hipStreamCreateWithFlags");
+      }
+    }
+  }
   auto kt = kernel_octant(*grid, p->R, p->m);
   int r = EXX_OK;
   if (is_plain(p)) {
@@ -420,6 +505,9 @@ void exx_plan_destroy(exx_plan* p) {
     (void)hipEventDestroy(p->ev_start[i]);
     (void)hipEventDestroy(p->ev_stop[i]);
   }
+  for (hipEvent_t e : p->sync_ev) (void)hipEventDestroy(e);
+  for (hipStream_t q : p->side)
+    if (q) (void)hipStreamDestroy(q);
   void* ptrs[] = {p->tables.tw, p->tables.md, p->tables.ktab, p->tables.tw_m, p->tables.ktab_m};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -468,11 +556,14 @@ int exx_plan_set_tuning(exx_plan* p, const exx_tuning* t) {
   if (!p || !t) return fail(EXX_ERR_INVALID_ARG, "plan or tuning is NULL");
   if (t->tile < 0 || t->tile > 16 || t->batch_slots < 0)
     return fail(EXX_ERR_INVALID_ARG, "tile must be in 1..16 (clamped to the pass limit) and batch_slots >= 0");
+  if (t->slab_threads != 0 && t->slab_threads != 256 && t->slab_threads != 512)
+    return fail(EXX_ERR_INVALID_ARG, "slab_threads must be 256 or 512");
+  if (t->streams != 0 && t->streams != 1 && t->streams != 3)
+    return fail(EXX_ERR_INVALID_ARG, "streams must be 1 or 3");
   if (t->tile) p->tuning.tile = t->tile;
   if (t->batch_slots) p->tuning.batch_slots = t->batch_slots;
-  if (t->zblock_a) p->tuning.zblock_a = t->zblock_a;
-  if (t->zblock_c) p->tuning.zblock_c = t->zblock_c;
   if (t->slab_threads) p->tuning.slab_threads = t->slab_threads;
+  if (t->streams) p->tuning.streams = t->streams;
   return EXX_OK;
 }
 

@@ -220,8 +220,8 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
       auto bar = line.find('|');
       if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
       exx_tuning t{};
-      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.tile, &t.batch_slots, &t.zblock_a,
-                      &t.zblock_c, &t.slab_threads) == 5)
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d", &t.tile, &t.batch_slots,
+                      &t.slab_threads, &t.streams) == 4)
         return exx_plan_set_tuning(p, &t);
     }
   }
@@ -229,7 +229,12 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   float best_ms = 1e30f;
   std::vector<int> tiles = {4, 8};
   std::vector<int> batches = {64, 256, 1 << 20};
-  std::vector<int> slab_threads = {256, 512};
+  const bool fused = p->precision != EXX_PREC_FP64_PLAIN;
+  // the 512-thread slab variant exists for the FP32 path at n = 64 only
+  std::vector<int> slab_threads = (p->n == 64 && p->precision == EXX_PREC_FP32)
+                                      ? std::vector<int>{256, 512}
+                                      : std::vector<int>{p->tuning.slab_threads};
+  std::vector<int> streams = fused ? std::vector<int>{1, 3} : std::vector<int>{1};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EXX_ERR_HIP;
   double* ex_dev = nullptr;
@@ -238,10 +243,12 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   for (int t : tiles) {
     for (int bs : batches) {
      for (int sth : slab_threads) {
+      for (int nst : streams) {
       exx_tuning cand = base;
       cand.tile = t;
       cand.batch_slots = bs;
       cand.slab_threads = sth;
+      cand.streams = nst;
       if (exx_plan_set_tuning(p, &cand) != EXX_OK) continue;
       size_t need = 0;
       if (exx_workspace_bytes(p, n_orb, &need) != EXX_OK || need > ws_bytes) continue;
@@ -260,6 +267,8 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
         best_ms = ms;
         best = cand;
       }
+      }
+      if (rc != EXX_OK) break;
      }
      if (rc != EXX_OK) break;
     }
@@ -272,8 +281,8 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   if (rc != EXX_OK) return rc;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    f << key.str() << "|" << best.tile << " " << best.batch_slots << " " << best.zblock_a << " "
-      << best.zblock_c << " " << best.slab_threads << "\n";
+    f << key.str() << "|" << best.tile << " " << best.batch_slots << " " << best.slab_threads
+      << " " << best.streams << "\n";
   }
   return exx_plan_prepare(p, n_orb);
 }

@@ -20,8 +20,10 @@
 // slot), the y/z classes are looped over inside pass B and summed after
 // demodulation.  Periodic grids have one class and no modulation.
 //
-// X layout per slot: [cx][kx][y][z] (z fastest), so pass B reads and writes
-// one contiguous n x n slab and passes A/C move rows of z-blocks.
+// X layout per slot, z-blocked: [y][z / 16][cx][kx][z % 16].  Passes A and C
+// work on the rows (y, 16 consecutive z) of every x-frequency, which is one
+// contiguous chunk of 2 n x 16 complex values; pass B gathers its slab
+// (cx, kx) as n^2 / 16 runs of 16 consecutive z.
 #include "exx_fft.hpp"
 #include "exx_internal.hpp"
 
@@ -35,6 +37,20 @@ struct SplitAC {  // x-lines of passes A and C: 16 work items per line in step 2
 };
 
 __device__ __forceinline__ int fold(int k, int M) { return k <= M - k ? k : M - k; }
+
+// z-block of the spectrum layout; passes A and C move one z-block of rows
+constexpr int XZ = 16;
+
+// offset of (cx, kx, y, z) within a slot, and of (y, z) within slab (cx, kx)
+template <int N, int NCLS>
+__device__ __forceinline__ size_t x_off(int cx, int kx, int y, int z) {
+  return ((size_t)(y * (N / XZ) + z / XZ) * NCLS * N + cx * N + kx) * XZ + (z % XZ);
+}
+__device__ __forceinline__ size_t slab_base(int slab) { return (size_t)slab * XZ; }
+template <int N, int NCLS>
+__device__ __forceinline__ int slab_off(int y, int z) {
+  return (y * (N / XZ) + z / XZ) * (NCLS * N * XZ) + (z % XZ);
+}
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -85,6 +101,7 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
   constexpr int NL = NCLS * ZB;  // lines per block
+  static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
   __shared__ cpx<T> zb[ZB * P];
   __shared__ cpx<T> wk[NL * P];
   __shared__ cpx<T> tw[N];
@@ -160,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
 #pragma unroll
       for (int q2 = 0; q2 < L2; ++q2) {
         int kx = q1 + L1 * q2;
-        Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi] = v[q2];
+        Xs[x_off<N, NCLS>(cx, kx, y, z0 + zi)] = v[q2];
       }
     }
   }
@@ -194,6 +211,7 @@ struct SlabFft {
   static __device__ __forceinline__ bool ok2(int it) { return C2 % NT == 0 || it < C2; }
 
   // y forward step 1 from the global slab (modulated by md^(cy y + cz z)) -> layout A
+  template <int NCLS>
   static __device__ __forceinline__ void y_fwd1(const cpx<T>* g, cpx<T>* lds, const cpx<T>* tw,
                                                 const cpx<T>* md, int cy, int cz, int tid) {
 #pragma unroll
@@ -205,7 +223,7 @@ struct SlabFft {
         cpx<T> mz = cz ? md[z] : cpx<T>{T(1), T(0)};
 #pragma unroll
         for (int k1 = 0; k1 < L1; ++k1) {
-          cpx<T> a = g[(t + L2 * k1) * N + z];
+          cpx<T> a = g[slab_off<N, NCLS>(t + L2 * k1, z)];
           if (cy) a = cmul(a, md[t + L2 * k1]);
           if (cz) a = cmul(a, mz);
           v[k1] = a;
@@ -386,7 +404,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
   const int cx = slab / N, kxp = slab % N;
   const int kxf = NCLS == 2 ? 2 * kxp + cx : kxp;
   const T* kt = ktab + (size_t)fold(kxf, M) * H * H;
-  cpx<T>* g = X + ((size_t)ls * NCLS * N + slab) * (size_t)(N * N);
+  cpx<T>* g = X + (size_t)ls * NCLS * N * N * N + slab_base(slab);
 
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
@@ -407,7 +425,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
     cpx<T>* Vb = lds + N * PB;
 #pragma unroll 1
     for (int cy = 0; cy < NCLS; ++cy) {
-      F::y_fwd1(g, U, tw, md, cy, 0, tid);
+      F::template y_fwd1<NCLS>(g, U, tw, md, cy, 0, tid);
       __syncthreads();
       F::template y_fwd2<false>(U, Vb, tid);
       __syncthreads();
@@ -482,7 +500,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
     for (int cls = 0; cls < NCLS * NCLS; ++cls) {
       const int cy = NCLS == 2 ? (cls >> 1) : 0;
       const int cz = NCLS == 2 ? (cls & 1) : 0;
-      F::y_fwd1(g, lds, tw, md, cy, cz, tid);
+      F::template y_fwd1<NCLS>(g, lds, tw, md, cy, cz, tid);
       __syncthreads();
       F::template y_fwd2<true>(lds, lds, tid);
       __syncthreads();
@@ -543,7 +561,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
       if (F::ok1(it)) {
         int z = it % N, t = it / N;
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) g[(t + L2 * k1) * N + z] = acc[ii][k1];
+        for (int k1 = 0; k1 < L1; ++k1) g[slab_off<N, NCLS>(t + L2 * k1, z)] = acc[ii][k1];
       }
     }
   }
@@ -599,6 +617,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   constexpr int NW = NT / 64;
   constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
   static_assert(ZB * L2 == NT, "one point-owner item per thread");
+  static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
   // Spectrum rows of the current slot.  One buffer suffices: the store of
   // slot k+1 follows the second barrier of slot k, after every read of xs.
   __shared__ cpx<T> xs[NL * P];
@@ -645,17 +664,15 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     for (int k1 = 0; k1 < L1; ++k1) accJ[b][k1] = 0.0;
   double ew = 0.0;
 
-  // spectrum rows of a slot: values p = tid + k NT -> (cx, kx, zi), zi fastest
+  // spectrum rows of a slot: the block's rows are one contiguous z-block chunk
+  // of the slot, values p = tid + q NT -> (cx, kx, zi), zi fastest
   cpx<T> pf[PF];
   auto fetch = [&](int k) {
-    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3;
+    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N;
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
       int p = tid + q * NT;
-      if ((NL * N) % NT == 0 || p < NL * N) {
-        int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
-        pf[q] = Xs[((size_t)(cx * N + kx) * N + y) * N + z0 + zi];
-      }
+      if ((NL * N) % NT == 0 || p < NL * N) pf[q] = Xs[p];
     }
   };
   // orbital values at the owned points: every J-side orbital of the tile once
@@ -931,12 +948,11 @@ constexpr int pass_b_threads() {
 
 template <typename T>
 hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slots, int slot0,
-                         int nslots, const double* occ, bool weighted, int zb, const Tables& tb) {
+                         int nslots, const double* occ, bool weighted, const Tables& tb) {
   if (nslots <= 0) return hipSuccess;
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
-    constexpr int ZB = 16;
+    constexpr int ZB = XZ;
     constexpr int NT = 256;
-    (void)zb;
     dim3 grid(N * (N / ZB), nslots);
     auto* Xc = static_cast<cpx<T>*>(X);
     auto* tw = static_cast<const cpx<T>*>(tb.tw);
@@ -1031,14 +1047,13 @@ template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
-                         bool pair_out, int zb, int tmax, const Tables& tb) {
+                         bool pair_out, int tmax, const Tables& tb) {
   if (ntiles <= 0) return hipSuccess;
-  (void)zb;
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
     if constexpr (sizeof(T) == 8 && N > 96) {
       return hipErrorInvalidValue;
     } else {
-      constexpr int ZB = 16;
+      constexpr int ZB = XZ;
       constexpr int NT = ZB * 16;
       constexpr int TM = pass_c_tile<N>();
       if (tmax > TM) return hipErrorInvalidValue;
@@ -1060,19 +1075,19 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
 }
 
 template hipError_t launch_pass_a<float>(const Launch&, const float*, void*, const Slot*, int, int,
-                                         const double*, bool, int, const Tables&);
+                                         const double*, bool, const Tables&);
 template hipError_t launch_pass_a<double>(const Launch&, const double*, void*, const Slot*, int,
-                                          int, const double*, bool, int, const Tables&);
+                                          int, const double*, bool, const Tables&);
 template hipError_t launch_pass_b<float>(const Launch&, void*, int, bool, double*, int,
                                          const Tables&, int);
 template hipError_t launch_pass_b<double>(const Launch&, void*, int, bool, double*, int,
                                           const Tables&, int);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
                                          const Slot*, const TilePair*, int, int, int, double*,
-                                         double*, bool, bool, bool, int, int, const Tables&);
+                                         double*, bool, bool, bool, int, const Tables&);
 template hipError_t launch_pass_c<double>(const Launch&, const void*, const double*,
                                           const double*, const Slot*, const TilePair*, int, int,
-                                          int, double*, double*, bool, bool, bool, int, int,
+                                          int, double*, double*, bool, bool, bool, int,
                                           const Tables&);
 
 }  // namespace exx

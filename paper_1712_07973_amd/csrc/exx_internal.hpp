@@ -49,6 +49,10 @@ struct exx_plan {
   size_t ev_used = 0;
   double prof_ms[EXX_PASS_KINDS] = {};
   long long prof_launches[EXX_PASS_KINDS] = {};
+  // overlapped rounds (tuning.streams == 3): side streams of passes A and C and
+  // the fork/join events of one evaluation (created before any graph capture)
+  hipStream_t side[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> sync_ev;
 };
 
 namespace exx {
@@ -60,7 +64,7 @@ hipError_t launch_zero(double* p, size_t count, hipStream_t s);
 
 template <typename T>
 hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slots, int slot0,
-                         int nslots, const double* occ, bool weighted, int zb, const Tables& tb);
+                         int nslots, const double* occ, bool weighted, const Tables& tb);
 template <typename T>
 hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
                          int slot0, const Tables& tb, int slab_threads);
@@ -68,7 +72,7 @@ template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
-                         bool pair_out, int zb, int tmax, const Tables& tb);
+                         bool pair_out, int tmax, const Tables& tb);
 int energy_parts(int n);  // pair-energy partials per slot half (fused passes)
 hipError_t launch_slot_reduce(const double* parts, int kparts, int count, int nhalves,
                               double* e_slot, hipStream_t s);
