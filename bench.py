@@ -119,17 +119,72 @@ def timed(plan, psi, occ, kpsi, ex, steps, warmup):
     if torch.distributed.is_available() and torch.distributed.is_initialized():
         torch.distributed.barrier()
     torch.cuda.synchronize()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps - 1)]
     t_host = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
+    for k in range(steps):
         plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+        if k < steps - 1:
+            marks[k].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_host
     ms = e0.elapsed_time(e1) / steps
+    edges = [e0] + marks + [e1]
+    per_step = sorted(edges[k].elapsed_time(edges[k + 1]) for k in range(steps))
     prof = plan.read_profile()
+    prof["_median_ms"] = (per_step[(steps - 1) // 2] + per_step[steps // 2]) / 2
     plan.enable_profiling(False)
     return ms, wall, prof
+
+
+def copy_bandwidth(dev, reps: int = 5) -> float:
+    """Device-to-device copy rate of 1 GiB (bytes read + bytes written per second)."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def autograd_times(grid, psi, occ, reps: int = 5) -> dict:
+    """Median forward (E_x only) and backward (recomputed K psi) times of exchange_energy."""
+    import torch
+
+    import paper_1712_07973_amd as exx
+    x = psi.clone().requires_grad_(True)
+    for _ in range(2):
+        exx.exchange_energy(x, occ, grid).backward()
+        x.grad = None
+    torch.cuda.synchronize()
+    fwd, bwd = [], []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        y = exx.exchange_energy(x, occ, grid)
+        ev[1].record()
+        y.backward()
+        ev[2].record()
+        torch.cuda.synchronize()
+        fwd.append(ev[0].elapsed_time(ev[1]))
+        bwd.append(ev[1].elapsed_time(ev[2]))
+        x.grad = None
+    fwd.sort()
+    bwd.sort()
+    return {"forward_ms": round(fwd[reps // 2], 4), "backward_ms": round(bwd[reps // 2], 4),
+            "forward": "E_x only (Parseval, no pass C)",
+            "backward": "K psi recomputed, gradient -2 f h^3 K psi"}
 
 
 def cpu_baseline(sysm, n_sample: int) -> dict:
@@ -252,6 +307,7 @@ def main(argv=None) -> int:
     E32 = float(ex.item())
     K32 = kpsi.clone()
 
+    median_ms = prof.pop("_median_ms")
     # dominant kernel and its roofline
     passes = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max(("pass_a", "pass_b", "pass_c"), key=lambda k: passes.get(k, (0, 0))[0])
@@ -285,6 +341,7 @@ def main(argv=None) -> int:
         "unit": "pair-solves/s",
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_per_step_median": round(median_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
@@ -318,6 +375,12 @@ def main(argv=None) -> int:
                 out["speedup_vs_fp64_plain"] = round(value / out[prec]["value"], 2)
             del p64, k64
             torch.cuda.empty_cache()
+
+    if not a.no_baselines:
+        copy_gbs = copy_bandwidth(dev)
+        out["copy_bandwidth_GBs"] = round(copy_gbs, 1)
+        roofline["hbm"]["frac_of_copy_bandwidth"] = round(achieved_gbs / copy_gbs, 4)
+        out["autograd"] = autograd_times(grid, psi, occ)
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sysm, min(a.cpu_sample, N))
