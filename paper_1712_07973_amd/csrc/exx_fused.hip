@@ -41,6 +41,10 @@ __device__ __forceinline__ int fold(int k, int M) { return k <= M - k ? k : M - 
 // z-block of the spectrum layout; passes A and C move one z-block of rows
 constexpr int XZ = 16;
 
+#ifndef PASS_A_SLOTS
+#define PASS_A_SLOTS 2  // slots per pass A block
+#endif
+
 // offset of (cx, kx, y, z) within a slot, and of (y, z) within slab (cx, kx)
 template <int N, int NCLS>
 __device__ __forceinline__ size_t x_off(int cx, int kx, int y, int z) {
@@ -89,18 +93,21 @@ __device__ __forceinline__ T sqrt_weight(const double* occ, int i, int j) {
 
 // ---------------------------------------------------------------------------
 // pass A: co-densities of two pairs packed as Z, forward x-transform per class
-// block: (y, z-block) x slot;  rows (y, z0..z0+ZB)
+// block: rows (y, z0..z0+ZB) of SPB consecutive slots.  The orbital values of
+// the next slot are loaded into registers before the current slot's
+// transform, so its loads overlap the current slot's LDS work and stores.
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NCLS, int ZB, int NT, bool W>
+template <typename T, int N, int NCLS, int ZB, int NT, int SPB, bool W>
 __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>* __restrict__ X,
                                                const Slot* __restrict__ slots, int slot0,
-                                               const double* __restrict__ occ,
+                                               int nslots, const double* __restrict__ occ,
                                                const cpx<T>* __restrict__ twg,
                                                const cpx<T>* __restrict__ mdg) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
-  constexpr int NL = NCLS * ZB;  // lines per block
+  constexpr int NL = NCLS * ZB;              // lines per block
+  constexpr int PV = (ZB * N + NT - 1) / NT;  // grid points per thread
   static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
   __shared__ cpx<T> zb[ZB * P];
   __shared__ cpx<T> wk[NL * P];
@@ -110,74 +117,101 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
   const int z0 = (blockIdx.x % (N / ZB)) * ZB;
-  const int ls = blockIdx.y;
-  const Slot sl = slots[slot0 + ls];
+  const int ls0 = blockIdx.y * SPB;
+  const int ls1 = ls0 + SPB < nslots ? ls0 + SPB : nslots;
   const size_t M3 = (size_t)N * N * N;
 
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
   }
-  const bool ha = sl.ia >= 0, hb = sl.ib >= 0;  // either half may be empty
-  T wa = T(1), wb = T(1);
-  if (W) {
-    if (ha) wa = sqrt_weight<T>(occ, sl.ia, sl.ja);
-    if (hb) wb = sqrt_weight<T>(occ, sl.ib, sl.jb);
-  }
-  const T* pia = psi + (size_t)(ha ? sl.ia : 0) * M3;
-  const T* pja = psi + (size_t)(ha ? sl.ja : 0) * M3;
-  const T* pib = psi + (size_t)(hb ? sl.ib : 0) * M3;
-  const T* pjb = psi + (size_t)(hb ? sl.jb : 0) * M3;
-  for (int p = tid; p < ZB * N; p += NT) {
-    int zi = p / N, x = p % N;
-    size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
-    T a = ha ? pia[o] * pja[o] * wa : T(0);
-    T b = hb ? pib[o] * pjb[o] * wb : T(0);
-    zb[zi * P + x] = {a, b};
-  }
-  __syncthreads();
-
-  // step 1: items (line, t), line = cx*ZB + zi fastest
-  constexpr int C1 = NL * L2;
+  // orbital values of slot ls at the block's points p = tid + q NT -> (zi, x)
+  T va[PV][2], vb[PV][2];
+  auto fetch = [&](int ls) {
+    const Slot sl = slots[slot0 + ls];
+    const bool ha = sl.ia >= 0, hb = sl.ib >= 0;  // either half may be empty
+    const T* pia = psi + (size_t)(ha ? sl.ia : 0) * M3;
+    const T* pja = psi + (size_t)(ha ? sl.ja : 0) * M3;
+    const T* pib = psi + (size_t)(hb ? sl.ib : 0) * M3;
+    const T* pjb = psi + (size_t)(hb ? sl.jb : 0) * M3;
 #pragma unroll
-  for (int it0 = 0; it0 < C1; it0 += NT) {
-    int it = it0 + tid;
-    if (C1 % NT == 0 || it < C1) {
-      int line = it % NL, t = it / NL;
-      int cx = line / ZB, zi = line % ZB;
-      cpx<T> v[L1];
-#pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) {
-        int x = t + L2 * k1;
-        v[k1] = zb[zi * P + x];
-        if (NCLS == 2 && cx == 1) v[k1] = cmul(v[k1], md[x]);
+    for (int q = 0; q < PV; ++q) {
+      const int p = tid + q * NT;
+      if ((ZB * N) % NT == 0 || p < ZB * N) {
+        const int zi = p / N, x = p % N;
+        const size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
+        va[q][0] = ha ? pia[o] : T(0);
+        va[q][1] = ha ? pja[o] : T(0);
+        vb[q][0] = hb ? pib[o] : T(0);
+        vb[q][1] = hb ? pjb[o] : T(0);
       }
-      Dft<L1, -1, T>::run(v);
-#pragma unroll
-      for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
-#pragma unroll
-      for (int q1 = 0; q1 < L1; ++q1) wk[line * P + t + L2 * q1] = v[q1];
     }
-  }
-  __syncthreads();
+  };
+  if (ls0 < ls1) fetch(ls0);
 
-  // step 2: items (line, q1); DFT_L2 over t -> kx = q1 + L1 q2, written to X
-  constexpr int C2 = NL * L1;
-  cpx<T>* Xs = X + (size_t)ls * NCLS * M3;
+#pragma unroll 1
+  for (int ls = ls0; ls < ls1; ++ls) {
+    T wa = T(1), wb = T(1);
+    if (W) {
+      const Slot sl = slots[slot0 + ls];
+      if (sl.ia >= 0) wa = sqrt_weight<T>(occ, sl.ia, sl.ja);
+      if (sl.ib >= 0) wb = sqrt_weight<T>(occ, sl.ib, sl.jb);
+    }
+    // zb was last read by the previous slot's step 1, before its second barrier
 #pragma unroll
-  for (int it0 = 0; it0 < C2; it0 += NT) {
-    int it = it0 + tid;
-    if (C2 % NT == 0 || it < C2) {
-      int line = it % NL, q1 = it / NL;
-      int cx = line / ZB, zi = line % ZB;
-      cpx<T> v[L2];
+    for (int q = 0; q < PV; ++q) {
+      const int p = tid + q * NT;
+      if ((ZB * N) % NT == 0 || p < ZB * N) {
+        const int zi = p / N, x = p % N;
+        zb[zi * P + x] = {va[q][0] * va[q][1] * wa, vb[q][0] * vb[q][1] * wb};
+      }
+    }
+    if (ls + 1 < ls1) fetch(ls + 1);
+    __syncthreads();
+
+    // step 1: items (line, t), line = cx*ZB + zi fastest; wk was last read by the
+    // previous slot's step 2, before the barrier above
+    constexpr int C1 = NL * L2;
 #pragma unroll
-      for (int t = 0; t < L2; ++t) v[t] = wk[line * P + t + L2 * q1];
-      Dft<L2, -1, T>::run(v);
+    for (int it0 = 0; it0 < C1; it0 += NT) {
+      int it = it0 + tid;
+      if (C1 % NT == 0 || it < C1) {
+        int line = it % NL, t = it / NL;
+        int cx = line / ZB, zi = line % ZB;
+        cpx<T> v[L1];
 #pragma unroll
-      for (int q2 = 0; q2 < L2; ++q2) {
-        int kx = q1 + L1 * q2;
-        Xs[x_off<N, NCLS>(cx, kx, y, z0 + zi)] = v[q2];
+        for (int k1 = 0; k1 < L1; ++k1) {
+          int x = t + L2 * k1;
+          v[k1] = zb[zi * P + x];
+          if (NCLS == 2 && cx == 1) v[k1] = cmul(v[k1], md[x]);
+        }
+        Dft<L1, -1, T>::run(v);
+#pragma unroll
+        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) wk[line * P + t + L2 * q1] = v[q1];
+      }
+    }
+    __syncthreads();
+
+    // step 2: items (line, q1); DFT_L2 over t -> kx = q1 + L1 q2, written to X
+    constexpr int C2 = NL * L1;
+    cpx<T>* Xs = X + (size_t)ls * NCLS * M3;
+#pragma unroll
+    for (int it0 = 0; it0 < C2; it0 += NT) {
+      int it = it0 + tid;
+      if (C2 % NT == 0 || it < C2) {
+        int line = it % NL, q1 = it / NL;
+        int cx = line / ZB, zi = line % ZB;
+        cpx<T> v[L2];
+#pragma unroll
+        for (int t = 0; t < L2; ++t) v[t] = wk[line * P + t + L2 * q1];
+        Dft<L2, -1, T>::run(v);
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) {
+          int kx = q1 + L1 * q2;
+          Xs[x_off<N, NCLS>(cx, kx, y, z0 + zi)] = v[q2];
+        }
       }
     }
   }
@@ -953,24 +987,25 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
     constexpr int ZB = XZ;
     constexpr int NT = 256;
-    dim3 grid(N * (N / ZB), nslots);
+    constexpr int SPB = PASS_A_SLOTS;
+    dim3 grid(N * (N / ZB), (nslots + SPB - 1) / SPB);
     auto* Xc = static_cast<cpx<T>*>(X);
     auto* tw = static_cast<const cpx<T>*>(tb.tw);
     auto* md = static_cast<const cpx<T>*>(tb.md);
     if (L.ncls == 2) {
       if (weighted)
-        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, true>), grid, dim3(NT), 0, L.stream, psi,
-                           Xc, slots, slot0, occ, tw, md);
+        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, SPB, true>), grid, dim3(NT), 0, L.stream,
+                           psi, Xc, slots, slot0, nslots, occ, tw, md);
       else
-        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, false>), grid, dim3(NT), 0, L.stream, psi,
-                           Xc, slots, slot0, occ, tw, md);
+        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, SPB, false>), grid, dim3(NT), 0, L.stream,
+                           psi, Xc, slots, slot0, nslots, occ, tw, md);
     } else {
       if (weighted)
-        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, true>), grid, dim3(NT), 0, L.stream, psi,
-                           Xc, slots, slot0, occ, tw, md);
+        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, SPB, true>), grid, dim3(NT), 0, L.stream,
+                           psi, Xc, slots, slot0, nslots, occ, tw, md);
       else
-        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, false>), grid, dim3(NT), 0, L.stream, psi,
-                           Xc, slots, slot0, occ, tw, md);
+        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, SPB, false>), grid, dim3(NT), 0, L.stream,
+                           psi, Xc, slots, slot0, nslots, occ, tw, md);
     }
     return hipGetLastError();
   });
