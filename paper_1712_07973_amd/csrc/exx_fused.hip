@@ -262,13 +262,46 @@ struct SlabFft {
           if (cz) a = cmul(a, mz);
           v[k1] = a;
         }
-        Dft<L1, -1, T>::run(v);
-#pragma unroll
-        for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
-#pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * N + z] = v[q1];
+        y_fwd1_tail(v, lds, tw, z, t);
       }
     }
+  }
+  // the same for class (1, 0) from slab values already in registers
+  static __device__ __forceinline__ void y_fwd1_odd_vals(const cpx<T> (&vals)[I1][L1], cpx<T>* lds,
+                                                         const cpx<T>* tw, const cpx<T>* md,
+                                                         int tid) {
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (ok1(it)) {
+        int z = it % N, t = it / N;
+        cpx<T> v[L1];
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) v[k1] = cmul(vals[ii][k1], md[t + L2 * k1]);
+        y_fwd1_tail(v, lds, tw, z, t);
+      }
+    }
+  }
+  // slab values of items (z, t), y = t + L2 k1, into registers
+  template <int NCLS>
+  static __device__ __forceinline__ void load_slab(const cpx<T>* g, cpx<T> (&vals)[I1][L1], int tid) {
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      int it = tid + ii * NT;
+      if (ok1(it)) {
+        int z = it % N, t = it / N;
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) vals[ii][k1] = g[slab_off<N, NCLS>(t + L2 * k1, z)];
+      }
+    }
+  }
+  static __device__ __forceinline__ void y_fwd1_tail(cpx<T>* v, cpx<T>* lds, const cpx<T>* tw,
+                                                     int z, int t) {
+    Dft<L1, -1, T>::run(v);
+#pragma unroll
+    for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+    for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * N + z] = v[q1];
   }
   // y forward step 2: layout A (src) -> layout B (dst), ky in natural order;
   // in place (src == dst) every item is loaded before any is stored
@@ -457,9 +490,16 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
     // registers), which removes the in-place and write-after-read barriers
     cpx<T>* U = lds;
     cpx<T>* Vb = lds + N * PB;
-#pragma unroll 1
+    static_assert(!SHARE_Y || NCLS == 2, "shared y-transforms serve two z classes");
+    // the slab again for the odd y class, loaded (an L2 hit) while the even
+    // class finishes, into registers its y-columns no longer need
+    cpx<T> odd[I1][L1];
+#pragma unroll
     for (int cy = 0; cy < NCLS; ++cy) {
-      F::template y_fwd1<NCLS>(g, U, tw, md, cy, 0, tid);
+      if (cy == 0)
+        F::template y_fwd1<NCLS>(g, U, tw, md, 0, 0, tid);
+      else
+        F::y_fwd1_odd_vals(odd, U, tw, md, tid);
       __syncthreads();
       F::template y_fwd2<false>(U, Vb, tid);
       __syncthreads();
@@ -510,6 +550,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
         }
       }
       if (EONLY) {
+        if (cy == 0) F::template load_slab<NCLS>(g, odd, tid);
         __syncthreads();
         continue;
       }
@@ -523,6 +564,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
           for (int k1 = 0; k1 < L1; ++k1) U[(t + L2 * k1) * PB + ky] = wacc[ii][k1];
         }
       }
+      if (cy == 0) F::template load_slab<NCLS>(g, odd, tid);
       __syncthreads();
       F::template y_inv2<false>(U, Vb, tw, tid);
       __syncthreads();
