@@ -23,6 +23,7 @@ import numpy as np
 
 PERIODIC = "periodic"
 FREE = "free"
+SURFACE = "surface"  # periodic in x and y, isolated along z
 
 
 @dataclass(frozen=True)
@@ -31,8 +32,10 @@ class OrbitalRecipe:
 
     n: grid points per axis; h: spacing (bohr); n_orb: number of orbitals;
     n_gauss: Gaussians per orbital; sigma: (lo, hi) of the uniform width draw;
-    centres: "box" (uniform in [0, L)^3, minimum image -- periodic systems) or
-    "middle" (uniform in [0.25 L, 0.75 L]^3 -- isolated systems);
+    centres: "box" (uniform in [0, L)^3, minimum image -- periodic systems),
+    "middle" (uniform in [0.25 L, 0.75 L]^3 -- isolated systems) or "slab"
+    (x, y uniform in [0, L) with minimum image, z in [0.25 L, 0.75 L] --
+    surface systems);
     ptype: multiply each Gaussian by a random p-type factor u.(r - A)/sigma;
     frac_last: number of trailing orbitals with occupation drawn U[0, 2];
     occ: occupation of the others.
@@ -68,17 +71,17 @@ def raw_gaussian_orbitals(rec: OrbitalRecipe, rng: np.random.Generator) -> np.nd
     three 1-D profiles (a p-factor is a sum of three separable terms).
     """
     n, h, L = rec.n, rec.h, rec.n * rec.h
-    periodic = rec.centres == "box"
+    # per axis (x, y, z): periodic placement with minimum image, or confined
+    periodic = {"box": (True, True, True), "middle": (False, False, False),
+                "slab": (True, True, False)}[rec.centres]
     phi = np.zeros((rec.n_orb, n, n, n), dtype=np.float64)
     for i in range(rec.n_orb):
         for _ in range(rec.n_gauss):
             coef = rng.uniform(-1.0, 1.0)
             s = rng.uniform(*rec.sigma)
-            if periodic:
-                A = rng.uniform(0.0, L, size=3)
-            else:
-                A = rng.uniform(0.25 * L, 0.75 * L, size=3)
-            dx, dy, dz = (_axis_displacement(n, h, A[k], periodic) for k in range(3))
+            A = np.array([rng.uniform(0.0, L) if periodic[k] else rng.uniform(0.25 * L, 0.75 * L)
+                          for k in range(3)])
+            dx, dy, dz = (_axis_displacement(n, h, A[k], periodic[k]) for k in range(3))
             gx, gy, gz = (np.exp(-d * d / (2.0 * s * s)) for d in (dx, dy, dz))
             if rec.ptype:
                 u = rng.normal(size=3)
@@ -160,5 +163,5 @@ class System:
 def make_system(rec: OrbitalRecipe, R: float | None = None) -> System:
     psi, occ = draw_system(rec)
     if R is None:
-        R = rec.n * rec.h if rec.bc == FREE else 0.0
+        R = rec.n * rec.h if rec.bc in (FREE, SURFACE) else 0.0
     return System(rec, psi, occ, float(R))

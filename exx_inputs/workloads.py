@@ -1,4 +1,4 @@
-"""The five named workloads (sizes, boundary conditions, seeds).
+"""The named workloads (sizes, boundary conditions, seeds).
 
 Each preset freezes one reading of a workload description: grid, spacing,
 orbital count and Gaussian recipe.  ``small`` variants keep the same recipe
@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .generator import FREE, PERIODIC, OrbitalRecipe, System, make_system
+from .generator import FREE, PERIODIC, SURFACE, OrbitalRecipe, System, make_system
 
 H = 0.4  # grid spacing in bohr for every workload
 
@@ -27,6 +27,11 @@ def recipe(name: str) -> OrbitalRecipe:
         # periodic 96^3, 128 orbitals of 8 p-type Gaussians each
         return OrbitalRecipe(n=96, h=H, n_orb=128, n_gauss=8, sigma=(0.8, 1.6),
                              centres="box", bc=PERIODIC, ptype=True, seed=1003)
+    if name == "surface64_n32":
+        # surface: periodic in x, y (L = 25.6 bohr), isolated along z (64 -> 128
+        # zero padded, interaction cut at |z - z'| = L); 32 orbitals
+        return OrbitalRecipe(n=64, h=H, n_orb=32, n_gauss=4, sigma=(0.6, 1.5),
+                             centres="slab", bc=SURFACE, seed=1006)
     if name == "free128_n256":
         # isolated, 128^3 grid zero-padded to 256^3, 256 orbitals, last 16 fractional
         return OrbitalRecipe(n=128, h=H, n_orb=256, n_gauss=4, sigma=(0.6, 1.5),
@@ -34,7 +39,7 @@ def recipe(name: str) -> OrbitalRecipe:
     raise KeyError(name)
 
 
-SINGLE = ("periodic32_n8", "free64_n32", "periodic96_n128", "free128_n256")
+SINGLE = ("periodic32_n8", "free64_n32", "periodic96_n128", "free128_n256", "surface64_n32")
 BATCH = "batch16_free"
 
 

@@ -28,6 +28,15 @@ design notes):
   as 8 pi sin^2(|G| R / 2) / |G|^2, its G = 0 limit 2 pi R^2 kept, and the
   potential cropped back to [0, n)^3; R defaults to L (the largest radius
   that the doubled box keeps free of images);
+* surface (periodic in x and y, isolated along z, one of the mixed boundary
+  conditions of Section 2.1.2): FFT grid n x n x 2n, zero padding along z
+  only, and the Coulomb interaction cut at |z - z'| = R (default L):
+  for G_par > 0
+      4 pi / G^2 [1 + exp(-G_par R) (G_z / G_par sin(G_z R) - cos(G_z R))],
+  for G_par = 0 the finite part, the transform of -2 pi |z| on |z| < R,
+      4 pi / G_z^2 [1 - cos(G_z R) - G_z R sin(G_z R)],   -2 pi R^2 at G = 0
+  (the in-plane integral of 1/r diverges at G_par = 0; dropping its constant
+  is the usual convention for a 2-D periodic array of charges);
 * G = 2 pi k / (m h) with k folded to the symmetric range (k > m/2 -> k - m).
 
 Parity pins: see tests/test_oracle_*.py (closed forms for plane waves and
@@ -43,6 +52,7 @@ import scipy.fft as sfft
 
 PERIODIC = "periodic"
 FREE = "free"
+SURFACE = "surface"  # periodic x, y; isolated z
 SCREENED = "screened"  # periodic-style erfc(omega r)/r kernel (screened hybrids)
 
 _WORKERS = int(os.environ.get("EXX_ORACLE_WORKERS", "0")) or (os.cpu_count() or 1)
@@ -50,7 +60,18 @@ _WORKERS = int(os.environ.get("EXX_ORACLE_WORKERS", "0")) or (os.cpu_count() or 
 
 def fft_size(n: int, bc: str) -> int:
     """FFT grid points per axis: n for periodic, 2n (zero padded) for free."""
+    if bc == SURFACE:
+        raise ValueError("the surface grid is not cubic: use fft_shape")
     return 2 * n if bc == FREE else n
+
+
+def fft_shape(n: int, bc: str) -> tuple:
+    """FFT grid in array order (z, y, x): padded axes have 2n points."""
+    if bc == FREE:
+        return (2 * n, 2 * n, 2 * n)
+    if bc == SURFACE:
+        return (2 * n, n, n)
+    return (n, n, n)
 
 
 def default_radius(n: int, h: float) -> float:
@@ -58,17 +79,48 @@ def default_radius(n: int, h: float) -> float:
     return n * h
 
 
+def wavevector_components(shape: tuple, h: float):
+    """G_z, G_y, G_x (broadcastable) on an FFT grid of the given (z, y, x) shape."""
+    out = []
+    for a, m in enumerate(shape):
+        k = np.fft.fftfreq(m, d=1.0 / m)  # 0, 1, .., m/2-1, -m/2, .., -1  (integers)
+        g = 2.0 * math.pi * k / (m * h)
+        sh = [1, 1, 1]
+        sh[a] = m
+        out.append(g.reshape(sh))
+    return out
+
+
 def wavevector_sq(m: int, h: float) -> np.ndarray:
     """|G|^2 on the m^3 FFT grid, array index order [kz][ky][kx]."""
-    k = np.fft.fftfreq(m, d=1.0 / m)  # 0, 1, .., m/2-1, -m/2, .., -1  (integers)
-    g = 2.0 * math.pi * k / (m * h)
-    g2 = g * g
-    return g2[:, None, None] + g2[None, :, None] + g2[None, None, :]
+    gz, gy, gx = wavevector_components((m, m, m), h)
+    return gz * gz + gy * gy + gx * gx
+
+
+def surface_kernel(n: int, h: float, R: float | None = None) -> np.ndarray:
+    """Coulomb kernel cut at |z - z'| = R, periodic in x and y (n x n x 2n grid)."""
+    if R is None or R <= 0.0:
+        R = default_radius(n, h)
+    gz, gy, gx = wavevector_components(fft_shape(n, SURFACE), h)
+    gp = np.sqrt(gx * gx + gy * gy) + 0.0 * gz  # in-plane |G|, full shape
+    gzf = gz + 0.0 * gp
+    G2 = gp * gp + gzf * gzf
+    out = np.empty_like(G2)
+    par = gp > 0.0
+    cz, sz = np.cos(gzf * R), np.sin(gzf * R)
+    out[par] = (4.0 * math.pi / G2[par]) * (
+        1.0 + np.exp(-gp[par] * R) * (gzf[par] / gp[par] * sz[par] - cz[par]))
+    line = (~par) & (gzf != 0.0)
+    out[line] = (4.0 * math.pi / G2[line]) * (1.0 - cz[line] - gzf[line] * R * sz[line])
+    out[(~par) & (gzf == 0.0)] = -2.0 * math.pi * R * R
+    return out
 
 
 def kernel_hat(n: int, h: float, bc: str, R: float | None = None,
                omega: float = 0.0) -> np.ndarray:
     """Fourier-space Green's kernel on the FFT grid (real, even in G)."""
+    if bc == SURFACE:
+        return surface_kernel(n, h, R)
     m = fft_size(n, bc)
     G2 = wavevector_sq(m, h)
     out = np.zeros_like(G2)
@@ -93,12 +145,14 @@ def kernel_hat(n: int, h: float, bc: str, R: float | None = None,
     return out
 
 
-def embed(rho: np.ndarray, m: int) -> np.ndarray:
-    """Place an n^3 array in the first octant of an m^3 zero array."""
+def embed(rho: np.ndarray, m) -> np.ndarray:
+    """Place an n^3 array at the origin corner of a zero array of shape m
+    (an int for a cube, or a (z, y, x) shape)."""
     n = rho.shape[0]
-    if m == n:
+    shape = (m, m, m) if np.isscalar(m) else tuple(m)
+    if shape == rho.shape:
         return rho
-    out = np.zeros((m, m, m), dtype=rho.dtype)
+    out = np.zeros(shape, dtype=rho.dtype)
     out[:n, :n, :n] = rho
     return out
 
@@ -110,10 +164,10 @@ def solve_poisson(rho: np.ndarray, h: float, bc: str, R: float | None = None,
     V = crop( IFFT( K^ . FFT( embed(rho) ) ) ); rho is real so V is real.
     """
     n = rho.shape[0]
-    m = fft_size(n, bc)
+    shape = fft_shape(n, bc)
     if khat is None:
         khat = kernel_hat(n, h, bc, R, omega)
-    F = sfft.fftn(embed(rho, m), workers=_WORKERS)
+    F = sfft.fftn(embed(rho, shape), workers=_WORKERS)
     V = sfft.ifftn(khat * F, workers=_WORKERS)
     V = V[:n, :n, :n]
     return np.ascontiguousarray(V.real)
@@ -204,19 +258,19 @@ def realspace_kernel(n: int, h: float, bc: str, R: float | None = None,
     exponential matrices (O(m^4)), so that only the kernel formula is shared
     with the FFT route.
     """
-    m = fft_size(n, bc)
+    mz, my, mx = fft_shape(n, bc)
     khat = kernel_hat(n, h, bc, R, omega)
-    idx = np.arange(m)
-    E = np.exp(2j * math.pi * np.outer(idx, idx) / m)  # E[d, k]
-    K = np.einsum("ak,bl,cq,klq->abc", E, E, E, khat, optimize=True) / m ** 3
+    E = [np.exp(2j * math.pi * np.outer(np.arange(m), np.arange(m)) / m) for m in (mz, my, mx)]
+    K = np.einsum("ak,bl,cq,klq->abc", E[0], E[1], E[2], khat, optimize=True) / (mz * my * mx)
     return K.real
 
 
 def brute_force_potential(rho: np.ndarray, h: float, bc: str, R: float | None = None,
                           omega: float = 0.0) -> np.ndarray:
-    """V(g) = sum_{g'} rho(g') K((g - g') mod m), an explicit O(n^3 m^3) sum."""
+    """V(g) = sum_{g'} rho(g') K((g - g') mod m), an explicit O(n^3 m^3) sum
+    (m per axis)."""
     n = rho.shape[0]
-    m = fft_size(n, bc)
+    mz, my, mx = fft_shape(n, bc)
     K = realspace_kernel(n, h, bc, R, omega)
     V = np.zeros((n, n, n))
     src = np.argwhere(np.ones((n, n, n), dtype=bool))
@@ -224,8 +278,8 @@ def brute_force_potential(rho: np.ndarray, h: float, bc: str, R: float | None = 
         w = rho[a, b, c]
         if w == 0.0:
             continue
-        za = (np.arange(n) - a) % m
-        yb = (np.arange(n) - b) % m
-        xc = (np.arange(n) - c) % m
+        za = (np.arange(n) - a) % mz
+        yb = (np.arange(n) - b) % my
+        xc = (np.arange(n) - c) % mx
         V += w * K[np.ix_(za, yb, xc)]
     return V

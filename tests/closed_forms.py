@@ -117,3 +117,59 @@ def periodic_screened_pair_energy(Q: float, c: float, L: float, omega: float, km
     terms = (Q * Q) * np.exp(-G2[nz] * c * c) * 4.0 * math.pi * (-np.expm1(-G2[nz] / (4 * omega ** 2))) / G2[nz]
     total = math.fsum(np.sort(terms).tolist()) + Q * Q * math.pi / omega ** 2
     return total / L ** 3
+
+
+def _slab_mean_exp(G: np.ndarray, d: float, s: float) -> np.ndarray:
+    """E[exp(-G |u|)] for u ~ N(d, s^2), G > 0 (two erfc terms, scaled to avoid overflow)."""
+    from scipy.special import erfcx
+    # 1/2 e^{G^2 s^2/2} [e^{-G d} erfc((G s^2 - d)/(s sqrt2)) + e^{G d} erfc((G s^2 + d)/(s sqrt2))]
+    # with erfc(x) = erfcx(x) e^{-x^2}: each term becomes erfcx(.) e^{-d^2 / (2 s^2)}
+    a = (G * s * s - d) / (s * math.sqrt(2.0))
+    b = (G * s * s + d) / (s * math.sqrt(2.0))
+    g = math.exp(-d * d / (2.0 * s * s))
+    ta = np.where(a > 0, erfcx(np.maximum(a, 0)) * g,
+                  np.exp(G * G * s * s / 2.0 - G * d) * (2.0 - erfcx(np.maximum(-a, 0)) * np.exp(-a * a)))
+    tb = np.where(b > 0, erfcx(np.maximum(b, 0)) * g,
+                  np.exp(G * G * s * s / 2.0 + G * d) * (2.0 - erfcx(np.maximum(-b, 0)) * np.exp(-b * b)))
+    return 0.5 * (ta + tb)
+
+
+def slab_gaussian_interaction(Q1, P1, c1, Q2, P2, c2, L: float, kmax: int) -> float:
+    """int int Q1 N(P1,c1)(r) Q2 N(P2,c2)(r') v(r - r') for a square cell L x L
+    periodic in x and y and no images along z, v = 1/|r| with the in-plane
+    G = 0 term taken as the transform of -2 pi |z - z'| (charged-sheet
+    convention).  Lattice sum over in-plane G = 2 pi (kx, ky) / L, |k| <= kmax:
+
+      (2 pi Q1 Q2 / A) [ sum_{G != 0} e^{-G^2 s^2 / 2} cos(G . D) E[e^{-G|u|}] / G - E|u| ]
+
+    with u = z - z' ~ N(d, s^2), s^2 = c1^2 + c2^2, d = P1z - P2z, D the
+    in-plane offset of the centres.
+    """
+    P1 = np.asarray(P1, float)
+    P2 = np.asarray(P2, float)
+    s = math.sqrt(c1 * c1 + c2 * c2)
+    d = float(P1[2] - P2[2])
+    Dx, Dy = float(P1[0] - P2[0]), float(P1[1] - P2[1])
+    k = np.arange(-kmax, kmax + 1)
+    KX, KY = np.meshgrid(k, k, indexing="ij")
+    gx = 2.0 * math.pi * KX / L
+    gy = 2.0 * math.pi * KY / L
+    G = np.sqrt(gx * gx + gy * gy)
+    nz = G > 0
+    Gn = G[nz]
+    terms = (np.exp(-Gn * Gn * s * s / 2.0) * np.cos(gx[nz] * Dx + gy[nz] * Dy)
+             * _slab_mean_exp(Gn, d, s) / Gn)
+    mean_abs = s * math.sqrt(2.0 / math.pi) * math.exp(-d * d / (2.0 * s * s)) + d * math.erf(d / (s * math.sqrt(2.0)))
+    total = math.fsum(np.sort(terms).tolist()) - mean_abs
+    return 2.0 * math.pi * Q1 * Q2 / (L * L) * total
+
+
+def slab_gaussian_self_energy(Q: float, c: float, L: float, kmax: int) -> float:
+    """The d = 0, same-Gaussian case: (2 pi Q^2 / A)[sum_{G != 0} erfc(G c) / G - 2 c / sqrt(pi)]."""
+    from scipy.special import erfc as _erfc
+    k = np.arange(-kmax, kmax + 1)
+    KX, KY = np.meshgrid(k, k, indexing="ij")
+    G = 2.0 * math.pi * np.sqrt(KX * KX + KY * KY).astype(np.float64) / L
+    Gn = G[G > 0]
+    total = math.fsum(np.sort(_erfc(Gn * c) / Gn).tolist()) - 2.0 * c / math.sqrt(math.pi)
+    return 2.0 * math.pi * Q * Q / (L * L) * total
