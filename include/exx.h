@@ -48,7 +48,16 @@ extern "C" {
 #endif
 
 /* ---- enumerations ------------------------------------------------------ */
-enum exx_bc { EXX_BC_PERIODIC = 0, EXX_BC_FREE = 1 };
+/* Boundary conditions (Section 2.1.2 lists free, surface and periodic ones).
+ *   PERIODIC: periodic in x, y, z; kernel 4 pi / G^2, G = 0 dropped;
+ *   FREE    : isolated; zero padding to 2n per axis, Coulomb cut at |r| = R;
+ *   SURFACE : periodic in x and y, isolated along z; zero padding to 2n along
+ *             z only, Coulomb cut at |z| = R:
+ *               4 pi / G^2 [1 + e^{-Gp R} (Gz / Gp sin(Gz R) - cos(Gz R))], Gp > 0,
+ *               4 pi / Gz^2 [1 - cos(Gz R) - Gz R sin(Gz R)],  Gp = 0 (the in-plane
+ *               G = 0 part is the transform of -2 pi |z|), -2 pi R^2 at G = 0,
+ *             with Gp the in-plane and Gz the normal wave vector. */
+enum exx_bc { EXX_BC_PERIODIC = 0, EXX_BC_FREE = 1, EXX_BC_SURFACE = 2 };
 
 /* Kernel of the pair Poisson problem.  COULOMB is 1/r (Eq. 4; truncated at R
  * for free boundaries).  SCREENED is erfc(omega r)/r, the short-range kernel of
@@ -91,7 +100,8 @@ typedef struct exx_grid {
   double hx, hy, hz; /* spacings in bohr, > 0 */
   int bc;            /* enum exx_bc */
   int kernel;        /* enum exx_kernel */
-  double R;          /* free-boundary truncation radius; <= 0 selects the default */
+  double R;          /* truncation radius (FREE: |r|, SURFACE: |z|); <= 0 selects the box
+                        length n h (along z for SURFACE) */
   double omega;      /* screening parameter for EXX_KERNEL_SCREENED (> 0) */
 } exx_grid;
 

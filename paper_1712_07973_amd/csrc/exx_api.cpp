@@ -47,8 +47,10 @@ bool supported_n(int n) { return n >= 16 && n <= 128 && n % 16 == 0; }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Green's kernel in Fourier space (real, even), FP64 on the host.
-double kernel_value(const exx_grid& g, double R, double G2) {
+// Green's kernel in Fourier space (real, even), FP64 on the host, at the
+// wave vector with in-plane (x, y) part Gp2 = Gx^2 + Gy^2 and normal part Gz.
+double kernel_value(const exx_grid& g, double R, double Gp2, double Gz) {
+  const double G2 = Gp2 + Gz * Gz;
   if (g.kernel == EXX_KERNEL_SCREENED) {
     double w2 = g.omega * g.omega;
     if (G2 == 0.0) return kPi / w2;
@@ -58,28 +60,35 @@ double kernel_value(const exx_grid& g, double R, double G2) {
     if (G2 == 0.0) return 0.0;
     return 4.0 * kPi / G2;
   }
+  if (g.bc == EXX_BC_SURFACE) {  // Coulomb cut at |z| = R, periodic in-plane
+    if (Gp2 > 0.0) {
+      const double Gp = std::sqrt(Gp2);
+      return 4.0 * kPi / G2 *
+             (1.0 + std::exp(-Gp * R) * (Gz / Gp * std::sin(Gz * R) - std::cos(Gz * R)));
+    }
+    if (Gz != 0.0) return 4.0 * kPi / G2 * (1.0 - std::cos(Gz * R) - Gz * R * std::sin(Gz * R));
+    return -2.0 * kPi * R * R;
+  }
   if (G2 == 0.0) return 2.0 * kPi * R * R;
   double G = std::sqrt(G2);
   double s = std::sin(0.5 * G * R);
   return 8.0 * kPi * s * s / G2;
 }
 
-// Octant table K(fx, fy, fz) / m^3 for folded indices 0..m/2 (fz fastest).
-std::vector<double> kernel_octant(const exx_grid& g, double R, int m) {
-  const int H = m / 2 + 1;
-  std::vector<double> t((size_t)H * H * H);
-  const double inv = 1.0 / ((double)m * m * m);
-  const double hs[3] = {g.hx, g.hy, g.hz};
-  double Gc[3][130 * 2];
-  for (int a = 0; a < 3; ++a)
-    for (int f = 0; f < H; ++f) {
-      double G = 2.0 * kPi * f / (m * hs[a]);
-      Gc[a][f] = G * G;
-    }
-  for (int fx = 0; fx < H; ++fx)
-    for (int fy = 0; fy < H; ++fy)
-      for (int fz = 0; fz < H; ++fz)
-        t[((size_t)fx * H + fy) * H + fz] = kernel_value(g, R, Gc[0][fx] + Gc[1][fy] + Gc[2][fz]) * inv;
+// Octant table K(fx, fy, fz) / (mx my mz) for folded indices 0..m/2 per axis
+// (fz fastest).
+std::vector<double> kernel_octant(const exx_grid& g, double R, Dims m) {
+  const int hx = m.x / 2 + 1, hy = m.y / 2 + 1, hz = m.z / 2 + 1;
+  std::vector<double> t((size_t)hx * hy * hz);
+  const double inv = 1.0 / ((double)m.x * m.y * m.z);
+  auto wave = [](int f, int mm, double h) { return 2.0 * kPi * f / (mm * h); };
+  for (int fx = 0; fx < hx; ++fx)
+    for (int fy = 0; fy < hy; ++fy)
+      for (int fz = 0; fz < hz; ++fz) {
+        const double gx = wave(fx, m.x, g.hx), gy = wave(fy, m.y, g.hy);
+        t[((size_t)fx * hy + fy) * hz + fz] =
+            kernel_value(g, R, gx * gx + gy * gy, wave(fz, m.z, g.hz)) * inv;
+      }
   return t;
 }
 
@@ -106,8 +115,8 @@ bool is_fp32(const exx_plan* p) { return p->precision == EXX_PREC_FP32; }
 bool is_plain(const exx_plan* p) { return p->precision == EXX_PREC_FP64_PLAIN; }
 
 size_t slot_bytes(const exx_plan* p) {
-  // fused: ncls * n^3 complex of the compute type; plain: m^3 complex FP64 per pair
-  if (is_plain(p)) return (size_t)p->m * p->m * p->m * 16;
+  // fused: ncls * n^3 complex of the compute type; plain: the padded grid, complex FP64 per pair
+  if (is_plain(p)) return (size_t)p->m.x * p->m.y * p->m.z * 16;
   size_t c = is_fp32(p) ? 8 : 16;
   return (size_t)p->ncls * p->n * p->n * p->n * c;
 }
@@ -255,7 +264,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     EXX_PROF(EXX_PASS_ZERO);
     if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
   }
-  Launch L{p->n, p->ncls, p->m, p->h3, st};
+  Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st};
   const bool overlap = p->tuning.streams == 3 && p->side[0] && p->side[1] &&
                        p->sync_ev.size() >= 1 + 3 * s.segments.size();
   if (!overlap) {
@@ -375,7 +384,7 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     }
     for (int a = 0; a < 3; ++a) {
       EXX_PROF(EXX_PASS_PLAIN_FFT);
-      EXX_HIP(plain_fft_axis(Z, np, p->m, a, -1, p->tables, st));
+      EXX_HIP(plain_fft_axis(Z, np, p->n, p->m, a, -1, p->tables, st));
     }
     {
       EXX_PROF(EXX_PASS_PLAIN_OTHER);
@@ -383,7 +392,7 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     }
     for (int a = 0; a < 3; ++a) {
       EXX_PROF(EXX_PASS_PLAIN_FFT);
-      EXX_HIP(plain_fft_axis(Z, np, p->m, a, +1, p->tables, st));
+      EXX_HIP(plain_fft_axis(Z, np, p->n, p->m, a, +1, p->tables, st));
     }
     {
       EXX_PROF(EXX_PASS_PLAIN_OTHER);
@@ -405,7 +414,8 @@ int validate_grid(const exx_grid* g, int precision) {
   if (!(g->hx > 0) || !(g->hy > 0) || !(g->hz > 0) || !std::isfinite(g->hx) || !std::isfinite(g->hy) ||
       !std::isfinite(g->hz))
     return fail(EXX_ERR_INVALID_ARG, "grid spacings must be positive and finite");
-  if (g->bc != EXX_BC_PERIODIC && g->bc != EXX_BC_FREE) return fail(EXX_ERR_INVALID_ARG, "unknown boundary condition");
+  if (g->bc != EXX_BC_PERIODIC && g->bc != EXX_BC_FREE && g->bc != EXX_BC_SURFACE)
+    return fail(EXX_ERR_INVALID_ARG, "unknown boundary condition");
   if (g->kernel != EXX_KERNEL_COULOMB && g->kernel != EXX_KERNEL_SCREENED)
     return fail(EXX_ERR_INVALID_ARG, "unknown kernel");
   if (g->kernel == EXX_KERNEL_SCREENED && (!(g->omega > 0) || g->bc != EXX_BC_PERIODIC))
@@ -455,10 +465,18 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
   if (!p) return fail(EXX_ERR_INTERNAL, "out of host memory");
   p->grid = *grid;
   p->n = grid->nx;
+  // parity classes per axis: 2 on zero-padded (isolated) axes
   p->ncls = grid->bc == EXX_BC_FREE ? 2 : 1;
-  p->m = p->ncls * p->n;
+  p->cy = grid->bc == EXX_BC_FREE ? 2 : 1;
+  p->cz = grid->bc == EXX_BC_PERIODIC ? 1 : 2;
+  p->m = Dims{p->ncls * p->n, p->cy * p->n, p->cz * p->n};
   p->h3 = grid->hx * grid->hy * grid->hz;
-  p->R = grid->R > 0 ? grid->R : p->n * std::min(grid->hx, std::min(grid->hy, grid->hz));
+  if (grid->R > 0)
+    p->R = grid->R;
+  else if (grid->bc == EXX_BC_SURFACE)
+    p->R = p->n * grid->hz;
+  else
+    p->R = p->n * std::min(grid->hx, std::min(grid->hy, grid->hz));
   p->precision = precision;
   p->n_orb_max = n_orb_max;
   default_tuning(p);
@@ -479,7 +497,8 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
   auto kt = kernel_octant(*grid, p->R, p->m);
   int r = EXX_OK;
   if (is_plain(p)) {
-    r = upload(&p->tables.tw_m, roots<double>(p->m, p->m));
+    r = upload(&p->tables.tw_n, roots<double>(p->n, p->n));
+    if (!r && grid->bc != EXX_BC_PERIODIC) r = upload(&p->tables.tw_2n, roots<double>(2 * p->n, 2 * p->n));
     if (!r) r = upload(&p->tables.ktab_m, kt);
   } else if (is_fp32(p)) {
     std::vector<float> kf(kt.begin(), kt.end());
@@ -508,7 +527,8 @@ void exx_plan_destroy(exx_plan* p) {
   for (hipEvent_t e : p->sync_ev) (void)hipEventDestroy(e);
   for (hipStream_t q : p->side)
     if (q) (void)hipStreamDestroy(q);
-  void* ptrs[] = {p->tables.tw, p->tables.md, p->tables.ktab, p->tables.tw_m, p->tables.ktab_m};
+  void* ptrs[] = {p->tables.tw, p->tables.md, p->tables.ktab, p->tables.tw_n, p->tables.tw_2n,
+                  p->tables.ktab_m};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (auto& kv : p->schedules) {

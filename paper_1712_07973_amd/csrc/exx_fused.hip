@@ -339,11 +339,13 @@ struct SlabFft {
     for (int q1 = 0; q1 < L1; ++q1) lds[(t + L2 * q1) * PB + ky] = v[q1];
   }
   // z forward step 2, kernel multiply (or Parseval sum), inverse step 2, in place
-  template <bool EONLY, int M>
+  // kt: the kernel table plane of this slab, [fold ky][fold kz] with MY, MZ
+  // FFT points along y and z (2N on a zero-padded axis)
+  template <bool EONLY, int MY, int MZ>
   static __device__ __forceinline__ void z_mid(cpx<T>* lds, const cpx<T>* tw, const T* kt,
                                                int cy, int cz, double& esum, int tid) {
-    constexpr int H = M / 2 + 1;
-    constexpr bool PAD = (M == 2 * N);
+    constexpr int HZ = MZ / 2 + 1;
+    constexpr bool PADY = (MY == 2 * N), PADZ = (MZ == 2 * N);
 #pragma unroll
     for (int ii = 0; ii < I2; ++ii) {
       int it = tid + ii * NT;
@@ -353,16 +355,16 @@ struct SlabFft {
 #pragma unroll
         for (int t = 0; t < L2; ++t) v[t] = lds[(t + L2 * q1) * PB + ky];
         Dft<L2, -1, T>::run(v);
-        const int kyf = PAD ? 2 * ky + cy : ky;
-        const T* kr = kt + (size_t)fold(kyf, M) * H;
+        const int kyf = PADY ? 2 * ky + cy : ky;
+        const T* kr = kt + (size_t)fold(kyf, MY) * HZ;
         // kz = q1 + L1 q2 and its kernel index kzf = c + step q2 (c = 2 q1 + cz
         // padded, q1 periodic): below half the range fold(kzf) = kzf, above it
-        // M - kzf, with the switch exactly at q2 = L2 / 2, so both halves are a
+        // MZ - kzf, with the switch exactly at q2 = L2 / 2, so both halves are a
         // base pointer plus compile-time offsets.
-        constexpr int step = PAD ? 2 * L1 : L1;
-        const int c = PAD ? 2 * q1 + cz : q1;
+        constexpr int step = PADZ ? 2 * L1 : L1;
+        const int c = PADZ ? 2 * q1 + cz : q1;
         const T* k_lo = kr + c;
-        const T* k_hi = kr + (M - c);
+        const T* k_hi = kr + (MZ - c);
 #pragma unroll
         for (int q2 = 0; q2 < L2; ++q2) {
           T kv = (2 * q2 < L2) ? k_lo[step * q2] : k_hi[-step * q2];
@@ -451,7 +453,7 @@ constexpr int pass_b_min_waves() {
   return (SHARE_Y && NT == 512 && sizeof(T) == 4) ? 4 : 1;
 }
 
-template <typename T, int N, int NCLS, int NT, bool EONLY, bool SHARE_Y>
+template <typename T, int N, int CX, int CY, int CZ, int NT, bool EONLY, bool SHARE_Y>
 __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k_pass_b(cpx<T>* __restrict__ X, const T* __restrict__ ktab,
                                                const cpx<T>* __restrict__ twg,
                                                const cpx<T>* __restrict__ mdg,
@@ -459,8 +461,9 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
                                                int kparts) {
   using F = SlabFft<T, N, NT>;
   constexpr int L1 = F::L1, L2 = F::L2, PB = F::PB, I1 = F::I1;
-  constexpr int M = NCLS * N;
-  constexpr int H = M / 2 + 1;
+  constexpr int MX = CX * N, MY = CY * N, MZ = CZ * N;  // FFT points per axis
+  constexpr int HY = MY / 2 + 1, HZ = MZ / 2 + 1;       // kernel table extents
+  constexpr bool ANY_PAD = CX == 2 || CY == 2 || CZ == 2;
   __shared__ cpx<T> lds[(SHARE_Y ? 2 : 1) * N * PB];
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
@@ -469,13 +472,13 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
   const int slab = blockIdx.x;  // cx * N + kx
   const int ls = blockIdx.y;
   const int cx = slab / N, kxp = slab % N;
-  const int kxf = NCLS == 2 ? 2 * kxp + cx : kxp;
-  const T* kt = ktab + (size_t)fold(kxf, M) * H * H;
-  cpx<T>* g = X + (size_t)ls * NCLS * N * N * N + slab_base(slab);
+  const int kxf = CX == 2 ? 2 * kxp + cx : kxp;
+  const T* kt = ktab + (size_t)fold(kxf, MX) * HY * HZ;
+  cpx<T>* g = X + (size_t)ls * CX * N * N * N + slab_base(slab);
 
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
-    if (NCLS == 2) md[k] = mdg[k];
+    if (ANY_PAD) md[k] = mdg[k];
   }
   cpx<T> acc[I1][L1];
 #pragma unroll
@@ -490,14 +493,14 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
     // registers), which removes the in-place and write-after-read barriers
     cpx<T>* U = lds;
     cpx<T>* Vb = lds + N * PB;
-    static_assert(!SHARE_Y || NCLS == 2, "shared y-transforms serve two z classes");
+    static_assert(!SHARE_Y || CZ == 2, "shared y-transforms serve two z classes");
     // the slab again for the odd y class, loaded (an L2 hit) while the even
     // class finishes, into registers its y-columns no longer need
     cpx<T> odd[I1][L1];
 #pragma unroll
-    for (int cy = 0; cy < NCLS; ++cy) {
+    for (int cy = 0; cy < CY; ++cy) {
       if (cy == 0)
-        F::template y_fwd1<NCLS>(g, U, tw, md, 0, 0, tid);
+        F::template y_fwd1<CX>(g, U, tw, md, 0, 0, tid);
       else
         F::y_fwd1_odd_vals(odd, U, tw, md, tid);
       __syncthreads();
@@ -518,7 +521,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
         }
       }
 #pragma unroll
-      for (int cz = 0; cz < NCLS; ++cz) {
+      for (int cz = 0; cz < CZ; ++cz) {
         cpx<T>* B = cz ? Vb : U;  // class cz works in its own buffer
 #pragma unroll
         for (int ii = 0; ii < I1; ++ii) {
@@ -533,7 +536,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
           }
         }
         __syncthreads();
-        F::template z_mid<EONLY, M>(B, tw, kt, cy, cz, esum, tid);
+        F::template z_mid<EONLY, MY, MZ>(B, tw, kt, cy, cz, esum, tid);
         __syncthreads();
         if (EONLY) continue;
 #pragma unroll
@@ -550,7 +553,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
         }
       }
       if (EONLY) {
-        if (cy == 0) F::template load_slab<NCLS>(g, odd, tid);
+        if (cy == 0 && CY == 2) F::template load_slab<CX>(g, odd, tid);
         __syncthreads();
         continue;
       }
@@ -564,7 +567,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
           for (int k1 = 0; k1 < L1; ++k1) U[(t + L2 * k1) * PB + ky] = wacc[ii][k1];
         }
       }
-      if (cy == 0) F::template load_slab<NCLS>(g, odd, tid);
+      if (cy == 0 && CY == 2) F::template load_slab<CX>(g, odd, tid);
       __syncthreads();
       F::template y_inv2<false>(U, Vb, tw, tid);
       __syncthreads();
@@ -573,10 +576,10 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
     }
   } else {
 #pragma unroll 1
-    for (int cls = 0; cls < NCLS * NCLS; ++cls) {
-      const int cy = NCLS == 2 ? (cls >> 1) : 0;
-      const int cz = NCLS == 2 ? (cls & 1) : 0;
-      F::template y_fwd1<NCLS>(g, lds, tw, md, cy, cz, tid);
+    for (int cls = 0; cls < CY * CZ; ++cls) {
+      const int cy = cls / CZ;
+      const int cz = cls % CZ;
+      F::template y_fwd1<CX>(g, lds, tw, md, cy, cz, tid);
       __syncthreads();
       F::template y_fwd2<true>(lds, lds, tid);
       __syncthreads();
@@ -592,7 +595,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
         }
       }
       __syncthreads();
-      F::template z_mid<EONLY, M>(lds, tw, kt, cy, cz, esum, tid);
+      F::template z_mid<EONLY, MY, MZ>(lds, tw, kt, cy, cz, esum, tid);
       __syncthreads();
       if (EONLY) continue;
 #pragma unroll
@@ -637,7 +640,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
       if (F::ok1(it)) {
         int z = it % N, t = it / N;
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) g[slab_off<N, NCLS>(t + L2 * k1, z)] = acc[ii][k1];
+        for (int k1 = 0; k1 < L1; ++k1) g[slab_off<N, CX>(t + L2 * k1, z)] = acc[ii][k1];
       }
     }
   }
@@ -1060,30 +1063,34 @@ constexpr bool pass_b_share_y() {
   return sizeof(T) == 4 ? N <= 64 : N <= 32;
 }
 
-template <typename T, int N, int NT, bool SY>
-hipError_t launch_pass_b_nt(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
-                            double* e_slot, int slot0, const Tables& tb) {
+template <typename T, int N, int CX, int CY, int CZ, int NT, bool SY>
+hipError_t launch_pass_b_cls(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
+                             double* e_slot, int slot0, const Tables& tb) {
   auto* kt = static_cast<const T*>(tb.ktab);
   auto* tw = static_cast<const cpx<T>*>(tb.tw);
   auto* md = static_cast<const cpx<T>*>(tb.md);
-  if (L.ncls == 2) {
-    dim3 grid(2 * N, nslots);
-    if (energy_only)
-      hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, true, SY>), grid, dim3(NT), 0, L.stream, Xc, kt,
-                         tw, md, e_slot, slot0, energy_parts(N));
-    else
-      hipLaunchKernelGGL((k_pass_b<T, N, 2, NT, false, SY>), grid, dim3(NT), 0, L.stream, Xc, kt,
-                         tw, md, e_slot, slot0, energy_parts(N));
-  } else {
-    dim3 grid(N, nslots);
-    if (energy_only)
-      hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, true, false>), grid, dim3(NT), 0, L.stream, Xc,
-                         kt, tw, md, e_slot, slot0, energy_parts(N));
-    else
-      hipLaunchKernelGGL((k_pass_b<T, N, 1, NT, false, false>), grid, dim3(NT), 0, L.stream, Xc,
-                         kt, tw, md, e_slot, slot0, energy_parts(N));
-  }
+  dim3 grid(CX * N, nslots);
+  if (energy_only)
+    hipLaunchKernelGGL((k_pass_b<T, N, CX, CY, CZ, NT, true, SY>), grid, dim3(NT), 0, L.stream,
+                       Xc, kt, tw, md, e_slot, slot0, energy_parts(N));
+  else
+    hipLaunchKernelGGL((k_pass_b<T, N, CX, CY, CZ, NT, false, SY>), grid, dim3(NT), 0, L.stream,
+                       Xc, kt, tw, md, e_slot, slot0, energy_parts(N));
   return hipGetLastError();
+}
+
+// parity classes (x, y, z) of the three boundary conditions: free (2, 2, 2),
+// surface (1, 1, 2), periodic (1, 1, 1); the shared-y variant needs two z classes
+template <typename T, int N, int NT, bool SY>
+hipError_t launch_pass_b_nt(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
+                            double* e_slot, int slot0, const Tables& tb) {
+  if (L.ncls == 2 && L.cy == 2 && L.cz == 2)
+    return launch_pass_b_cls<T, N, 2, 2, 2, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
+  if (L.ncls == 1 && L.cy == 1 && L.cz == 2)
+    return launch_pass_b_cls<T, N, 1, 1, 2, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
+  if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
+    return launch_pass_b_cls<T, N, 1, 1, 1, NT, false>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
+  return hipErrorInvalidValue;
 }
 
 template <typename T>

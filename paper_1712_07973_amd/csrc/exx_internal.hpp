@@ -17,14 +17,24 @@ namespace exx {
 // Device tables of one plan (precision-specific arrays are null when unused).
 struct Tables {
   void* tw = nullptr;      // w_n^k, k < n (fused paths), cpx<T>
-  void* md = nullptr;      // w_{2n}^r, r < n (free boundary modulation), cpx<T>
-  void* ktab = nullptr;    // kernel octant / (fft points), T, [(m/2+1)^3]
-  void* tw_m = nullptr;    // w_m^k, k < m (plain path), cpx<double>
-  void* ktab_m = nullptr;  // kernel octant / m^3 for the plain path, double
+  void* md = nullptr;      // w_{2n}^r, r < n (padded-axis modulation), cpx<T>
+  void* ktab = nullptr;    // kernel octant / (fft points), T, [mx/2+1][my/2+1][mz/2+1]
+  void* tw_n = nullptr;    // w_n^k, k < n (plain path, unpadded axes), cpx<double>
+  void* tw_2n = nullptr;   // w_2n^k, k < 2n (plain path, padded axes), cpx<double>
+  void* ktab_m = nullptr;  // kernel octant / (fft points) for the plain path, double
 };
 
+// FFT points per axis (n or 2n)
+struct Dims {
+  int x, y, z;
+};
+
+// Parity classes per axis: 2 on a zero-padded axis (the 2n-point transform
+// splits into two n-point ones), 1 on a periodic axis.
 struct Launch {
-  int n, ncls, m;  // grid, x-classes (1 periodic, 2 free), fft points per axis
+  int n;           // grid points per axis
+  int ncls;        // x classes (spectrum slots hold ncls n^3 values)
+  int cy, cz;      // y and z classes
   double h3;       // volume element
   hipStream_t stream;
 };
@@ -33,7 +43,8 @@ struct Launch {
 
 struct exx_plan {
   exx_grid grid;
-  int n = 0, m = 0, ncls = 1;
+  int n = 0, ncls = 1, cy = 1, cz = 1;  // grid, parity classes per axis
+  exx::Dims m{0, 0, 0};                 // FFT points per axis
   double h3 = 0, R = 0;
   int precision = 0;
   int n_orb_max = 0;
@@ -85,12 +96,12 @@ int pass_c_max_tile(int n);  // largest pair-tile edge pass C supports at grid n
 
 // ---- plain FP64 path, exx_plain.hip ---------------------------------------
 hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs_in_launch,
-                       int n, int m, void* Z, hipStream_t s);
-hipError_t plain_fft_axis(void* Z, int npairs, int m, int axis, int dir, const Tables& tb,
+                       int n, Dims m, void* Z, hipStream_t s);
+hipError_t plain_fft_axis(void* Z, int npairs, int n, Dims m, int axis, int dir, const Tables& tb,
                           hipStream_t s);
-hipError_t plain_kernel_mul(void* Z, int npairs, int m, const Tables& tb, hipStream_t s);
+hipError_t plain_kernel_mul(void* Z, int npairs, Dims m, const Tables& tb, hipStream_t s);
 hipError_t plain_reduce(const void* Z, const double* psi, const double* occ, const Slot* slots,
-                        int slot0, int npairs_in_launch, int n, int m, double h3, double* kpsi,
+                        int slot0, int npairs_in_launch, int n, Dims m, double h3, double* kpsi,
                         double* e_slot, bool want_k, bool want_e, hipStream_t s);
 
 }  // namespace exx

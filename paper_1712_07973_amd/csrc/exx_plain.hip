@@ -1,7 +1,7 @@
 // exx_plain.hip -- the plain FP64 GPU path (reference implementation on the GPU).
 //
 // One orbital pair per complex transform (imaginary part zero), the full
-// zero-padded m^3 grid stored in HBM, and one launch per stage: pair build,
+// zero-padded grid (2n on isolated axes, n on periodic ones) stored in HBM, and one launch per stage: pair build,
 // three forward axis transforms, kernel multiply, three inverse axis
 // transforms, reduction with FP64 atomics.  It follows the pair-sum scheme of
 // arXiv:1712.07973 (Eq. 5 with the kernels 1-3 of Section 2.1.1) with no
@@ -20,8 +20,8 @@ constexpr int kPitch = kLines + 1;
 __device__ __forceinline__ int foldk(int k, int M) { return k <= M - k ? k : M - k; }
 
 __global__ void k_plain_build(const double* __restrict__ psi, const Slot* __restrict__ slots,
-                              int slot0, int n, int m, cpx<double>* __restrict__ Z) {
-  const size_t m3 = (size_t)m * m * m;
+                              int slot0, int n, Dims m, cpx<double>* __restrict__ Z) {
+  const size_t m3 = (size_t)m.x * m.y * m.z;
   const size_t n3 = (size_t)n * n * n;
   const int p = blockIdx.y;
   const Slot sl = slots[slot0 + p];
@@ -30,7 +30,7 @@ __global__ void k_plain_build(const double* __restrict__ psi, const Slot* __rest
   const double* pj = psi + (size_t)sl.ja * n3;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < m3;
        idx += (size_t)gridDim.x * blockDim.x) {
-    int x = (int)(idx % m), y = (int)((idx / m) % m), z = (int)(idx / ((size_t)m * m));
+    int x = (int)(idx % m.x), y = (int)((idx / m.x) % m.y), z = (int)(idx / ((size_t)m.x * m.y));
     double r = 0.0;
     if (x < n && y < n && z < n) {
       size_t o = ((size_t)z * n + y) * n + x;
@@ -40,33 +40,36 @@ __global__ void k_plain_build(const double* __restrict__ psi, const Slot* __rest
   }
 }
 
+// Transforms of length L along one axis of the [z][y][x] array (x fastest),
+// kLines lines per block; the lines of a block are consecutive in x for the
+// y and z axes and consecutive rows for the x axis.
 template <int L, int DIR>
-__global__ __launch_bounds__(256) void k_plain_axis(cpx<double>* __restrict__ Z, int axis,
-                                                    const cpx<double>* __restrict__ twg) {
+__global__ __launch_bounds__(256) void k_plain_axis(cpx<double>* __restrict__ Z, Dims m,
+                                                    int axis, const cpx<double>* __restrict__ twg) {
   using S = Split<L>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int NT = 256;
   __shared__ cpx<double> buf[L * kPitch];
   __shared__ cpx<double> tw[L];
   const int tid = threadIdx.x;
-  const size_t m3 = (size_t)L * L * L;
-  const int groups = L * L / kLines;
+  const size_t m3 = (size_t)m.x * m.y * m.z;
+  const int groups = (int)(m3 / L / kLines);
   const int p = blockIdx.x / groups, g = blockIdx.x % groups;
   size_t base;
   size_t es, lstr;
-  if (axis == 0) {
-    base = (size_t)p * m3 + (size_t)g * kLines * L;
+  if (axis == 0) {  // lines along x: rows (z, y), kLines consecutive rows
+    base = (size_t)p * m3 + (size_t)g * kLines * m.x;
     es = 1;
-    lstr = L;
-  } else if (axis == 1) {
-    int z = g / (L / kLines), x0 = (g % (L / kLines)) * kLines;
-    base = (size_t)p * m3 + (size_t)z * L * L + x0;
-    es = L;
+    lstr = m.x;
+  } else if (axis == 1) {  // lines along y: (z, x), kLines consecutive x
+    int z = g / (m.x / kLines), x0 = (g % (m.x / kLines)) * kLines;
+    base = (size_t)p * m3 + (size_t)z * m.x * m.y + x0;
+    es = m.x;
     lstr = 1;
-  } else {
-    int y = g / (L / kLines), x0 = (g % (L / kLines)) * kLines;
-    base = (size_t)p * m3 + (size_t)y * L + x0;
-    es = (size_t)L * L;
+  } else {  // lines along z: (y, x), kLines consecutive x
+    int y = g / (m.x / kLines), x0 = (g % (m.x / kLines)) * kLines;
+    base = (size_t)p * m3 + (size_t)y * m.x + x0;
+    es = (size_t)m.x * m.y;
     lstr = 1;
   }
   for (int k = tid; k < L; k += NT) tw[k] = twg[k];
@@ -125,14 +128,14 @@ __global__ __launch_bounds__(256) void k_plain_axis(cpx<double>* __restrict__ Z,
   }
 }
 
-__global__ void k_plain_kmul(cpx<double>* __restrict__ Z, int m, const double* __restrict__ kt) {
-  const size_t m3 = (size_t)m * m * m;
-  const int H = m / 2 + 1;
+__global__ void k_plain_kmul(cpx<double>* __restrict__ Z, Dims m, const double* __restrict__ kt) {
+  const size_t m3 = (size_t)m.x * m.y * m.z;
+  const int hy = m.y / 2 + 1, hz = m.z / 2 + 1;
   cpx<double>* zp = Z + (size_t)blockIdx.y * m3;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < m3;
        idx += (size_t)gridDim.x * blockDim.x) {
-    int kx = (int)(idx % m), ky = (int)((idx / m) % m), kz = (int)(idx / ((size_t)m * m));
-    double k = kt[((size_t)foldk(kx, m) * H + foldk(ky, m)) * H + foldk(kz, m)];
+    int kx = (int)(idx % m.x), ky = (int)((idx / m.x) % m.y), kz = (int)(idx / ((size_t)m.x * m.y));
+    double k = kt[((size_t)foldk(kx, m.x) * hy + foldk(ky, m.y)) * hz + foldk(kz, m.z)];
     cpx<double> v = zp[idx];
     zp[idx] = {v.x * k, v.y * k};
   }
@@ -142,11 +145,11 @@ __global__ __launch_bounds__(256) void k_plain_reduce(const cpx<double>* __restr
                                                       const double* __restrict__ psi,
                                                       const double* __restrict__ occ,
                                                       const Slot* __restrict__ slots, int slot0,
-                                                      int n, int m, double* __restrict__ kpsi,
+                                                      int n, Dims m, double* __restrict__ kpsi,
                                                       double* __restrict__ e_slot, int want_k,
                                                       int want_e) {
   __shared__ double red[4];
-  const size_t m3 = (size_t)m * m * m;
+  const size_t m3 = (size_t)m.x * m.y * m.z;
   const size_t n3 = (size_t)n * n * n;
   const int p = blockIdx.y;
   const Slot sl = slots[slot0 + p];
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(256) void k_plain_reduce(const cpx<double>* __restr
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n3;
        o += (size_t)gridDim.x * blockDim.x) {
     int x = (int)(o % n), y = (int)((o / n) % n), z = (int)(o / ((size_t)n * n));
-    double V = zp[((size_t)z * m + y) * m + x].x;
+    double V = zp[((size_t)z * m.y + y) * m.x + x].x;
     double a = pi[o], b = pj[o];
     e += a * b * V;
     if (want_k) {
@@ -202,40 +205,44 @@ unsigned grid_for(size_t count) {
 
 }  // namespace
 
-hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs, int n, int m,
+hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs, int n, Dims m,
                        void* Z, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
-  size_t m3 = (size_t)m * m * m;
+  size_t m3 = (size_t)m.x * m.y * m.z;
   hipLaunchKernelGGL(k_plain_build, dim3(grid_for(m3), npairs), dim3(256), 0, s, psi, slots,
                      slot0, n, m, static_cast<cpx<double>*>(Z));
   return hipGetLastError();
 }
 
-hipError_t plain_fft_axis(void* Z, int npairs, int m, int axis, int dir, const Tables& tb,
+hipError_t plain_fft_axis(void* Z, int npairs, int n, Dims m, int axis, int dir, const Tables& tb,
                           hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
-  return dispatch_m(m, [&]<int L>() -> hipError_t {
-    dim3 grid((unsigned)(npairs * (L * L / kLines)));
+  const int len = axis == 0 ? m.x : (axis == 1 ? m.y : m.z);
+  const size_t m3 = (size_t)m.x * m.y * m.z;
+  // roots of the axis length: n points on periodic axes, 2n on padded ones
+  auto* tw = static_cast<const cpx<double>*>(len == 2 * n ? tb.tw_2n : tb.tw_n);
+  if (!tw || (len != n && len != 2 * n)) return hipErrorInvalidValue;
+  return dispatch_m(len, [&]<int L>() -> hipError_t {
+    dim3 grid((unsigned)(npairs * (m3 / L / kLines)));
     auto* Zc = static_cast<cpx<double>*>(Z);
-    auto* tw = static_cast<const cpx<double>*>(tb.tw_m);
     if (dir < 0)
-      hipLaunchKernelGGL((k_plain_axis<L, -1>), grid, dim3(256), 0, s, Zc, axis, tw);
+      hipLaunchKernelGGL((k_plain_axis<L, -1>), grid, dim3(256), 0, s, Zc, m, axis, tw);
     else
-      hipLaunchKernelGGL((k_plain_axis<L, 1>), grid, dim3(256), 0, s, Zc, axis, tw);
+      hipLaunchKernelGGL((k_plain_axis<L, 1>), grid, dim3(256), 0, s, Zc, m, axis, tw);
     return hipGetLastError();
   });
 }
 
-hipError_t plain_kernel_mul(void* Z, int npairs, int m, const Tables& tb, hipStream_t s) {
+hipError_t plain_kernel_mul(void* Z, int npairs, Dims m, const Tables& tb, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
-  size_t m3 = (size_t)m * m * m;
+  size_t m3 = (size_t)m.x * m.y * m.z;
   hipLaunchKernelGGL(k_plain_kmul, dim3(grid_for(m3), npairs), dim3(256), 0, s,
                      static_cast<cpx<double>*>(Z), m, static_cast<const double*>(tb.ktab_m));
   return hipGetLastError();
 }
 
 hipError_t plain_reduce(const void* Z, const double* psi, const double* occ, const Slot* slots,
-                        int slot0, int npairs, int n, int m, double h3, double* kpsi,
+                        int slot0, int npairs, int n, Dims m, double h3, double* kpsi,
                         double* e_slot, bool want_k, bool want_e, hipStream_t s) {
   (void)h3;
   if (npairs <= 0) return hipSuccess;

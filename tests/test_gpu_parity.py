@@ -1,8 +1,9 @@
 """GPU parity: the HIP paths (through the C ABI) against the FP64 oracle.
 
 Sizes span several pair tiles with a ragged last tile (N not a multiple of
-the tile edge), an odd number of pairs (a half-filled packed slot), both
-boundary conditions and the mixed radices 3, 5 and 7 of the supported grids.
+the tile edge), an odd number of pairs (a half-filled packed slot), the three
+boundary conditions (periodic, free, surface) and the mixed radices 3, 5 and 7
+of the supported grids.
 """
 import numpy as np
 import pytest
@@ -25,6 +26,10 @@ CASES = [
     ("free", 48, 3, 25, 0),
     ("periodic", 80, 3, 26, 0),
     ("free", 16, 9, 27, 2),
+    ("surface", 16, 5, 28, 1),
+    ("surface", 32, 9, 29, 0),
+    ("surface", 48, 4, 30, 0),
+    ("surface", 64, 3, 31, 0),
 ]
 
 
@@ -62,10 +67,11 @@ def test_fp32_path_within_tolerance(case):
     assert np.max(np.abs(P - ref["pair_e"])) <= 1e-6 * np.max(np.abs(ref["pair_e"]))
 
 
+@pytest.mark.parametrize("bc", ["free", "surface"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
-def test_energy_only_and_kpsi_only_modes(precision):
-    say(f"[modes] {precision}")
-    s, ref = oracle_result("free", 32, 6, 23, 0)
+def test_energy_only_and_kpsi_only_modes(precision, bc):
+    say(f"[modes] {precision} {bc}")
+    s, ref = oracle_result(bc, 32, 6, 23, 0)
     dev = torch.device("cuda", 0)
     psi = torch.from_numpy(s.psi).to(dev)
     occ = torch.from_numpy(s.occ).to(dev)
