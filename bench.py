@@ -34,6 +34,9 @@ FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "orbital-pair Poisson solves/s (E_x+Kψ) FP32-batched vs FP64, HBM GB/s"
 
 
+CLASSES = {"free": (2, 2, 2), "surface": (1, 1, 2), "periodic": (1, 1, 1)}  # per axis x, y, z
+
+
 def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int) -> dict:
     """Minimum HBM bytes of each pass of one evaluation (FP32 path).
 
@@ -54,19 +57,20 @@ def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int) -> dict:
     }
 
 
-def fft_flops(n: int, ncls: int, n_slots: int, share_y: bool) -> dict:
+def fft_flops(n: int, classes: tuple, n_slots: int, share_y: bool) -> dict:
     """Nominal 5 L log2 L flops per complex n-point line transform, per pass.
 
-    Pass A/C: ncls x-classes of n^2 lines.  Pass B, per slab of n^2 points:
-    with shared y-transforms ncls y-lines sets forward and inverse plus ncls^2
-    z-line sets forward and inverse (2n ncls (1 + ncls) lines), otherwise
-    4 n ncls^2 lines.
+    classes = (cx, cy, cz) parity classes per axis.  Pass A/C: cx x-classes of
+    n^2 lines.  Pass B, per slab (cx n slabs per slot) of n^2 points: with
+    shared y-transforms cy y-line sets forward and inverse plus cy cz z-line
+    sets forward and inverse (2n cy (1 + cz) lines), otherwise 4 n cy cz lines.
     """
+    cx, cy, cz = classes
     f = 5.0 * n * math.log2(n)
-    a = n_slots * ncls * n * n * f
-    per_slab = 2 * n * ncls * (1 + ncls) if share_y else 4 * n * ncls * ncls
-    b = n_slots * ncls * n * per_slab * f
-    c = n_slots * ncls * n * n * f
+    a = n_slots * cx * n * n * f
+    per_slab = 2 * n * cy * (1 + cz) if share_y else 4 * n * cy * cz
+    b = n_slots * cx * n * per_slab * f
+    c = n_slots * cx * n * n * f
     return {"pass_a": a, "pass_b": b, "pass_c": c}
 
 
@@ -136,6 +140,20 @@ def timed(plan, psi, occ, kpsi, ex, steps, warmup):
     prof["_median_ms"] = (per_step[(steps - 1) // 2] + per_step[steps // 2]) / 2
     plan.enable_profiling(False)
     return ms, wall, prof
+
+
+def workload_text(sysm, pairs: int) -> str:
+    """What the single-system workload is, with its sizes."""
+    n, h, N = sysm.n, sysm.h, sysm.n_orb
+    L = n * h
+    geom = {"free": f"free-BC {n}^3 grid padded to {2 * n}^3, h={h} bohr, R=L={L:g} bohr",
+            "surface": f"surface (periodic x, y; isolated z) {n}^3 grid padded to {n}x{n}x{2 * n}, "
+                       f"h={h} bohr, R=L={L:g} bohr",
+            "periodic": f"periodic {n}^3 grid, h={h} bohr"}[sysm.bc]
+    occ = "occupations 2" if float(sysm.occ.min()) == float(sysm.occ.max()) == 2.0 \
+        else "occupations 2 with fractional tail"
+    return (f"{geom}, {N} Loewdin-orthonormalised Gaussian orbitals, {occ}, "
+            f"{pairs} pair solves, E_x + K psi")
 
 
 def copy_bandwidth(dev, reps: int = 5) -> float:
@@ -290,8 +308,9 @@ def main(argv=None) -> int:
     sysm = system(a.workload)
     N, n = sysm.n_orb, sysm.n
     pairs = pair_count(N)
-    ncls = 2 if sysm.bc == "free" else 1
-    grid = exx.Grid(n=n, h=sysm.h, bc=sysm.bc, R=sysm.R if sysm.bc == "free" else None)
+    classes = CLASSES[sysm.bc]
+    ncls = classes[0]
+    grid = exx.Grid(n=n, h=sysm.h, bc=sysm.bc, R=sysm.R if sysm.bc in ("free", "surface") else None)
     psi = torch.from_numpy(sysm.psi).to(dev)
     occ = torch.from_numpy(sysm.occ).to(dev)
     kpsi = torch.empty_like(psi)
@@ -315,7 +334,7 @@ def main(argv=None) -> int:
     per_launch_ms = dom_ms / dom_launches
     launches_per_step = dom_launches / a.steps
     alg = algorithmic_bytes(n, ncls, N, n_slots)
-    flops = fft_flops(n, ncls, n_slots, share_y=(ncls == 2 and n <= 64))
+    flops = fft_flops(n, classes, n_slots, share_y=(classes[2] == 2 and n <= 64))
     bytes_per_launch = alg[dom] / launches_per_step
     achieved_gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
     achieved_tflops = flops[dom] / launches_per_step / (per_launch_ms * 1e-3) / 1e12
@@ -345,10 +364,9 @@ def main(argv=None) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "free-BC 64^3 grid padded to 128^3, h=0.4 bohr, R=L=25.6 bohr, "
-                               "32 Loewdin-orthonormalised Gaussian orbitals, occupations 2, "
-                               "528 pair solves, E_x + K psi",
-                   "preset": a.workload, "n": n, "fft_grid": ncls * n, "n_orb": N,
+        "config": {"workload": workload_text(sysm, pairs),
+                   "preset": a.workload, "n": n,
+                   "fft_grid": [c * n for c in classes], "n_orb": N,
                    "pairs": pairs, "packed_slots": n_slots, "tuning": plan.tuning},
         "roofline": roofline,
         "whole_step_algorithmic_GBs": round(whole_alg / (ms * 1e-3) / 1e9, 1),

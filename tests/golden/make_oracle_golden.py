@@ -33,6 +33,7 @@ PLANS = {
     "free64_n32": (True, 0, [0, 7, 31], 2048),
     "periodic96_n128": (False, 24, [3, 77], 2048),
     "free128_n256": (False, 12, [250], 2048),
+    "surface64_n32": (True, 0, [0, 7, 31], 2048),
 }
 
 

@@ -90,6 +90,11 @@ def test_free64_n32(precision):
     check("free64_n32", precision)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
+def test_surface64_n32(precision):
+    check("surface64_n32", precision)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64_fused"])
 def test_periodic96_n128(precision):
     check("periodic96_n128", precision)
