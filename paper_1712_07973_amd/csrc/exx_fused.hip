@@ -1018,11 +1018,15 @@ bool fused_supported(int precision, int n) {
   return true;
 }
 
-template <typename T, int N>
+template <typename T, int N, bool SY>
 constexpr int pass_b_threads() {
-  // a few items per thread; from N = 96 on LDS allows one block per CU, so
-  // the block takes the whole CU (16 waves) to keep per-thread arrays small
-  return N <= 32 ? 128 : (N <= 64 ? 256 : ((N <= 80 || sizeof(T) == 8) ? 512 : 1024));
+  // a few items per thread; where LDS allows one block per CU (the shared-y
+  // variant from N = 80 on, the single-buffer one from N = 96 on) the block
+  // takes the whole CU (16 waves) to keep per-thread arrays small
+  if (N <= 32) return 128;
+  if (N <= 64) return 256;
+  if (sizeof(T) == 8) return 512;
+  return (SY || N > 80) ? 1024 : 512;
 }
 
 template <typename T>
@@ -1056,11 +1060,15 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
   });
 }
 
-template <typename T, int N>
+template <typename T, int N, int CY, int CZ>
 constexpr bool pass_b_share_y() {
-  // sharing the y-transforms keeps two more slab-sized register arrays live;
-  // only where that does not spill
-  return sizeof(T) == 4 ? N <= 64 : N <= 32;
+  // sharing the y-transforms needs two z classes, two slab buffers in LDS
+  // (2 N (N+1) complex values) and keeps two more slab-sized register arrays
+  // live; used where that fits without spilling (measured at n = 80: pass B
+  // 6.98 -> 4.09 ms free, 2.44 -> 1.16 ms surface; n = 96 surface 4.34 -> 1.79)
+  if (CZ != 2) return false;
+  if (sizeof(T) == 8) return N <= 32;
+  return N <= 80 || (N <= 96 && CY == 1);
 }
 
 template <typename T, int N, int CX, int CY, int CZ, int NT, bool SY>
@@ -1080,17 +1088,20 @@ hipError_t launch_pass_b_cls(const Launch& L, cpx<T>* Xc, int nslots, bool energ
 }
 
 // parity classes (x, y, z) of the three boundary conditions: free (2, 2, 2),
-// surface (1, 1, 2), periodic (1, 1, 1); the shared-y variant needs two z classes
-template <typename T, int N, int NT, bool SY>
-hipError_t launch_pass_b_nt(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
-                            double* e_slot, int slot0, const Tables& tb) {
-  if (L.ncls == 2 && L.cy == 2 && L.cz == 2)
-    return launch_pass_b_cls<T, N, 2, 2, 2, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
-  if (L.ncls == 1 && L.cy == 1 && L.cz == 2)
-    return launch_pass_b_cls<T, N, 1, 1, 2, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
-  if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
-    return launch_pass_b_cls<T, N, 1, 1, 1, NT, false>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
-  return hipErrorInvalidValue;
+// surface (1, 1, 2), periodic (1, 1, 1)
+template <typename T, int N, int CX, int CY, int CZ>
+hipError_t launch_pass_b_for(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
+                             double* e_slot, int slot0, const Tables& tb, int slab_threads) {
+  constexpr bool SY = pass_b_share_y<T, N, CY, CZ>();
+  constexpr int NT = pass_b_threads<T, N, SY>();
+  if constexpr (SY && NT == 256 && sizeof(T) == 4 && N == 64) {
+    // the 512-thread variant: one item per thread, 4 waves per SIMD
+    if (slab_threads == 512)
+      return launch_pass_b_cls<T, N, CX, CY, CZ, 512, SY>(L, Xc, nslots, energy_only, e_slot,
+                                                           slot0, tb);
+  }
+  return launch_pass_b_cls<T, N, CX, CY, CZ, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0,
+                                                      tb);
 }
 
 template <typename T>
@@ -1101,15 +1112,17 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
     if constexpr (sizeof(T) == 8 && N > 96) {
       return hipErrorInvalidValue;
     } else {
-      constexpr int NT = pass_b_threads<T, N>();
-      constexpr bool SY = pass_b_share_y<T, N>();
       auto* Xc = static_cast<cpx<T>*>(X);
-      if constexpr (SY && NT == 256 && sizeof(T) == 4 && N == 64) {
-        // the 512-thread variant: one item per thread, 4 waves per SIMD
-        if (slab_threads == 512)
-          return launch_pass_b_nt<T, N, 512, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
-      }
-      return launch_pass_b_nt<T, N, NT, SY>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
+      if (L.ncls == 2 && L.cy == 2 && L.cz == 2)
+        return launch_pass_b_for<T, N, 2, 2, 2>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
+                                                slab_threads);
+      if (L.ncls == 1 && L.cy == 1 && L.cz == 2)
+        return launch_pass_b_for<T, N, 1, 1, 2>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
+                                                slab_threads);
+      if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
+        return launch_pass_b_for<T, N, 1, 1, 1>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
+                                                slab_threads);
+      return hipErrorInvalidValue;
     }
   });
 }

@@ -30,6 +30,8 @@ CASES = [
     ("surface", 32, 9, 29, 0),
     ("surface", 48, 4, 30, 0),
     ("surface", 64, 3, 31, 0),
+    ("free", 80, 3, 32, 0),
+    ("surface", 96, 3, 33, 0),
 ]
 
 
