@@ -142,8 +142,14 @@ int cap_slots(const exx_plan* p, const Schedule& s) {
 }
 
 struct WsLayout {
-  size_t psi32 = 0, e_slot = 0, e_part = 0, X = 0, total = 0;
+  size_t psi32 = 0, e_slot = 0, e_part = 0, X = 0, Y = 0, total = 0;
+  int split_slots = 0;  // slots per launch of the split pass B (0: not split)
 };
+
+bool uses_split(const exx_plan* p) { return pass_b_split(p->precision, p->n, p->ncls, p->cy, p->cz); }
+
+// bytes per slot of the split pass B scratch: ncls cy n^3 complex FP32
+size_t split_slot_bytes(const exx_plan* p) { return (size_t)p->ncls * p->cy * p->n * p->n * p->n * 8; }
 
 WsLayout layout(const exx_plan* p, const Schedule& s) {
   WsLayout w;
@@ -156,6 +162,13 @@ WsLayout layout(const exx_plan* p, const Schedule& s) {
   if (!is_plain(p)) off += align_up(2 * s.slots.size() * (size_t)energy_parts(p->n) * sizeof(double), 256);
   w.X = off;
   off += align_up((size_t)cap_slots(p, s) * slot_bytes(p), 256);
+  w.Y = off;
+  if (!is_plain(p) && uses_split(p)) {
+    // a few slots per launch: the scratch stays near the memory-side cache size
+    const size_t budget = (size_t)512 << 20;
+    w.split_slots = (int)std::max<size_t>(1, std::min<size_t>(cap_slots(p, s), budget / split_slot_bytes(p)));
+    off += align_up((size_t)w.split_slots * split_slot_bytes(p), 256);
+  }
   w.total = off;
   return w;
 }
@@ -265,6 +278,25 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
   }
   Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st};
+  // pass B over ns slots from slot s0 (spectra at Xs) on the stream of Lb: one
+  // launch, or the split form in groups of w.split_slots
+  auto pass_b = [&](const Launch& Lb, char* Xs, int s0, int ns) -> int {
+    if (w.split_slots == 0) {
+      EXX_PROF_ON(EXX_PASS_B, Lb.stream);
+      EXX_HIP(launch_pass_b<T>(Lb, Xs, ns, parseval, e_part, s0, p->tables, p->tuning.slab_threads));
+      return EXX_OK;
+    }
+    if constexpr (sizeof(T) == 4) {
+      for (int a = 0; a < ns; a += w.split_slots) {
+        const int k = std::min(w.split_slots, ns - a);
+        EXX_PROF_ON(EXX_PASS_B, Lb.stream);
+        EXX_HIP(launch_pass_b_split<T>(Lb, Xs + (size_t)a * sb, ws + w.Y, k, parseval, e_part, s0 + a,
+                                       p->tables));
+      }
+      return EXX_OK;
+    }
+    return fail(EXX_ERR_INTERNAL, "split pass B is FP32 only");
+  };
   const bool overlap = p->tuning.streams == 3 && p->side[0] && p->side[1] &&
                        p->sync_ev.size() >= 1 + 3 * s.segments.size();
   if (!overlap) {
@@ -274,10 +306,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
         EXX_PROF(EXX_PASS_A);
         EXX_HIP(launch_pass_a<T>(L, psiT, X, s.d_slots, c.s0, ns, occ, parseval, p->tables));
       }
-      {
-        EXX_PROF(EXX_PASS_B);
-        EXX_HIP(launch_pass_b<T>(L, X, ns, parseval, e_part, c.s0, p->tables, p->tuning.slab_threads));
-      }
+      if (int r = pass_b(L, X, c.s0, ns)) return r;
       if (!parseval) {
         for (int g = c.seg0; g < c.seg1; ++g) {
           const auto& sg = s.segments[g];
@@ -319,11 +348,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
         hipEvent_t ea = p->sync_ev[ev++];
         EXX_HIP(hipEventRecord(ea, sa));
         EXX_HIP(hipStreamWaitEvent(st, ea, 0));
-        {
-          EXX_PROF(EXX_PASS_B);
-          EXX_HIP(launch_pass_b<T>(L, Xg, a1 - a0, parseval, e_part, a0, p->tables,
-                                   p->tuning.slab_threads));
-        }
+        if (int r = pass_b(L, Xg, a0, a1 - a0)) return r;
         hipEvent_t eb = p->sync_ev[ev++];
         EXX_HIP(hipEventRecord(eb, st));
         if (parseval) {
@@ -350,7 +375,8 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     EXX_PROF(EXX_PASS_FINALIZE);
     double* eo = (mode & EXX_MODE_ENERGY) ? ex_out : nullptr;
     if (parseval) {  // one partial per (slot, slab)
-      EXX_HIP(launch_slot_reduce(e_part, kparts, p->ncls * p->n, 2 * (int)s.slots.size(), e_slot, st));
+      const int count = w.split_slots ? split_energy_parts_used(p->n, p->ncls) : p->ncls * p->n;
+      EXX_HIP(launch_slot_reduce(e_part, kparts, count, 2 * (int)s.slots.size(), e_slot, st));
       EXX_HIP(launch_finalize(s.d_slots, (int)s.slots.size(), occ, e_slot, N, p->h3, 1, eo, nullptr, st));
     } else if (pair_e) {  // one partial per (slot half, row block)
       EXX_HIP(launch_slot_reduce(e_part, kparts, p->n * p->n / 16, 2 * (int)s.slots.size(), e_slot, st));

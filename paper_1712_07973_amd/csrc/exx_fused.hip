@@ -647,6 +647,292 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
 }
 
 // ---------------------------------------------------------------------------
+// pass B split in three launches for slabs whose two LDS buffers do not fit
+// (free n >= 96, surface n >= 112, periodic n >= 96).  The 2-D transform of a
+// slab factorises into independent 1-D transforms along y (per z column) and
+// along z (per ky line), so each launch works on chunks of SC columns or
+// lines with small LDS tiles and many blocks per CU; the y-transformed
+// classes travel through a scratch Y[slot][slab][cy][ky][z] (L2 / memory-side
+// cache resident for the few slots of one launch):
+//   B1  per z-chunk: y-transform of every class cy       X -> Y
+//   B2  per ky-chunk: per cy, z-transform of every class cz, kernel multiply
+//       (or the Parseval sum), inverse z, demodulate, sum over cz   Y -> Y
+//   B3  per z-chunk: inverse y of every class, demodulate, sum     Y -> X
+// ---------------------------------------------------------------------------
+constexpr int SC = 16;  // columns (B1, B3) or lines (B2) per block
+
+template <typename T, int N, int CX, int CY, int NT>
+__global__ __launch_bounds__(NT) void k_pass_b1(const cpx<T>* __restrict__ X, cpx<T>* __restrict__ Y,
+                                                const cpx<T>* __restrict__ twg,
+                                                const cpx<T>* __restrict__ mdg) {
+  using S = Split<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int P = SC + 1;
+  __shared__ cpx<T> buf[N * P];  // [y][zi]
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+  const int tid = threadIdx.x;
+  const int z0 = blockIdx.x * SC, slab = blockIdx.y, ls = blockIdx.z;
+  const cpx<T>* g = X + (size_t)ls * CX * N * N * N + slab_base(slab);
+  cpx<T>* yo = Y + ((size_t)ls * CX * N + slab) * CY * N * N;
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    md[k] = mdg[k];
+  }
+  __syncthreads();
+  constexpr int C1 = SC * L2, C2 = SC * L1;
+#pragma unroll 1
+  for (int cy = 0; cy < CY; ++cy) {
+    // step 1, items (zi, t): y = t + L2 k1
+    for (int it = tid; it < C1; it += NT) {
+      const int zi = it % SC, t = it / SC;
+      cpx<T> v[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        const int y = t + L2 * k1;
+        cpx<T> a = g[slab_off<N, CX>(y, z0 + zi)];
+        v[k1] = cy ? cmul(a, md[y]) : a;
+      }
+      Dft<L1, -1, T>::run(v);
+#pragma unroll
+      for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+      for (int q1 = 0; q1 < L1; ++q1) buf[(t + L2 * q1) * P + zi] = v[q1];
+    }
+    __syncthreads();
+    // step 2, items (zi, q1): ky = q1 + L1 q2
+    cpx<T>* yc = yo + (size_t)cy * N * N;
+    for (int it = tid; it < C2; it += NT) {
+      const int zi = it % SC, q1 = it / SC;
+      cpx<T> w[L2];
+#pragma unroll
+      for (int t = 0; t < L2; ++t) w[t] = buf[(t + L2 * q1) * P + zi];
+      Dft<L2, -1, T>::run(w);
+#pragma unroll
+      for (int q2 = 0; q2 < L2; ++q2) yc[(size_t)(q1 + L1 * q2) * N + z0 + zi] = w[q2];
+    }
+    __syncthreads();  // buf is rewritten by the next class
+  }
+}
+
+template <typename T, int N, int CX, int CY, int CZ, int NT, bool EONLY>
+__global__ __launch_bounds__(NT) void k_pass_b2(cpx<T>* __restrict__ Y, const T* __restrict__ ktab,
+                                                const cpx<T>* __restrict__ twg,
+                                                const cpx<T>* __restrict__ mdg,
+                                                double* __restrict__ e_part, int slot0,
+                                                int kparts) {
+  using S = Split<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int P = SC + 1;
+  constexpr int MX = CX * N, MY = CY * N, MZ = CZ * N;
+  constexpr int HY = MY / 2 + 1, HZ = MZ / 2 + 1;
+  constexpr bool PADY = CY == 2, PADZ = CZ == 2;
+  __shared__ cpx<T> buf[N * P];  // [z'][kyi]
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+  __shared__ double red[NT / 64];
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * SC, slab = blockIdx.y, ls = blockIdx.z;
+  const int cx = slab / N, kxp = slab % N;
+  const int kxf = CX == 2 ? 2 * kxp + cx : kxp;
+  const T* kt = ktab + (size_t)fold(kxf, MX) * HY * HZ;
+  cpx<T>* yo = Y + ((size_t)ls * CX * N + slab) * CY * N * N;
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    md[k] = mdg[k];
+  }
+  __syncthreads();
+  constexpr int C1 = SC * L2, C2 = SC * L1;
+  constexpr int I1 = (C1 + NT - 1) / NT;
+  double esum = 0.0;
+#pragma unroll 1
+  for (int cy = 0; cy < CY; ++cy) {
+    cpx<T>* yc = yo + (size_t)cy * N * N;
+    // the lines' values, items (kyi, t): z = t + L2 k1, and their z-class sums
+    cpx<T> vals[I1][L1], wacc[I1][L1];
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      const int it = tid + ii * NT;
+      if (C1 % NT == 0 || it < C1) {
+        const int kyi = it % SC, t = it / SC;
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) {
+          vals[ii][k1] = yc[(size_t)(k0 + kyi) * N + t + L2 * k1];
+          wacc[ii][k1] = {T(0), T(0)};
+        }
+      }
+    }
+#pragma unroll
+    for (int cz = 0; cz < CZ; ++cz) {
+      // forward step 1 (per t) -> buf [z'][kyi]
+#pragma unroll
+      for (int ii = 0; ii < I1; ++ii) {
+        const int it = tid + ii * NT;
+        if (C1 % NT == 0 || it < C1) {
+          const int kyi = it % SC, t = it / SC;
+          cpx<T> v[L1];
+#pragma unroll
+          for (int k1 = 0; k1 < L1; ++k1) v[k1] = cz ? cmul(vals[ii][k1], md[t + L2 * k1]) : vals[ii][k1];
+          Dft<L1, -1, T>::run(v);
+#pragma unroll
+          for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[t * q1]);
+#pragma unroll
+          for (int q1 = 0; q1 < L1; ++q1) buf[(t + L2 * q1) * P + kyi] = v[q1];
+        }
+      }
+      __syncthreads();
+      // forward step 2 (per q1), kernel multiply, inverse step 2, in place
+      for (int it = tid; it < C2; it += NT) {
+        const int kyi = it % SC, q1 = it / SC;
+        cpx<T> v[L2];
+#pragma unroll
+        for (int t = 0; t < L2; ++t) v[t] = buf[(t + L2 * q1) * P + kyi];
+        Dft<L2, -1, T>::run(v);
+        const int ky = k0 + kyi;
+        const int kyf = PADY ? 2 * ky + cy : ky;
+        const T* kr = kt + (size_t)fold(kyf, MY) * HZ;
+        // kz = q1 + L1 q2, kernel index c + step q2 folded at q2 = L2 / 2
+        constexpr int step = PADZ ? 2 * L1 : L1;
+        const int c = PADZ ? 2 * q1 + cz : q1;
+        const T* k_lo = kr + c;
+        const T* k_hi = kr + (MZ - c);
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) {
+          const T kv = (2 * q2 < L2) ? k_lo[step * q2] : k_hi[-step * q2];
+          if (EONLY) {
+            esum += (double)kv * ((double)v[q2].x * (double)v[q2].x + (double)v[q2].y * (double)v[q2].y);
+          } else {
+            v[q2].x *= kv;
+            v[q2].y *= kv;
+          }
+        }
+        if (!EONLY) {
+          Dft<L2, 1, T>::run(v);
+#pragma unroll
+          for (int t = 1; t < L2; ++t) v[t] = cmulc(v[t], tw[t * q1]);
+#pragma unroll
+          for (int t = 0; t < L2; ++t) buf[(t + L2 * q1) * P + kyi] = v[t];
+        }
+      }
+      __syncthreads();
+      if (!EONLY) {
+        // inverse step 1 (per t), demodulate, sum over cz
+#pragma unroll
+        for (int ii = 0; ii < I1; ++ii) {
+          const int it = tid + ii * NT;
+          if (C1 % NT == 0 || it < C1) {
+            const int kyi = it % SC, t = it / SC;
+            cpx<T> v[L1];
+#pragma unroll
+            for (int q1 = 0; q1 < L1; ++q1) v[q1] = buf[(t + L2 * q1) * P + kyi];
+            Dft<L1, 1, T>::run(v);
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1)
+              wacc[ii][k1] = cadd(wacc[ii][k1], cz ? cmulc(v[k1], md[t + L2 * k1]) : v[k1]);
+          }
+        }
+        __syncthreads();  // buf is rewritten by the next class
+      }
+    }
+    if (!EONLY) {
+#pragma unroll
+      for (int ii = 0; ii < I1; ++ii) {
+        const int it = tid + ii * NT;
+        if (C1 % NT == 0 || it < C1) {
+          const int kyi = it % SC, t = it / SC;
+#pragma unroll
+          for (int k1 = 0; k1 < L1; ++k1) yc[(size_t)(k0 + kyi) * N + t + L2 * k1] = wacc[ii][k1];
+        }
+      }
+    }
+  }
+  if (EONLY) {
+    // one partial per (slot, slab, ky-chunk), summed in a fixed order later
+    double v = esum;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int k = 0; k < NT / 64; ++k) sum += red[k];
+      e_part[(size_t)(2 * (slot0 + ls)) * kparts + (size_t)slab * (N / SC) + blockIdx.x] = sum;
+    }
+  }
+}
+
+template <typename T, int N, int CX, int CY, int NT>
+__global__ __launch_bounds__(NT) void k_pass_b3(cpx<T>* __restrict__ X, const cpx<T>* __restrict__ Y,
+                                                const cpx<T>* __restrict__ twg,
+                                                const cpx<T>* __restrict__ mdg) {
+  using S = Split<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int P = SC + 1;
+  __shared__ cpx<T> buf[N * P];  // [y'][zi]
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+  const int tid = threadIdx.x;
+  const int z0 = blockIdx.x * SC, slab = blockIdx.y, ls = blockIdx.z;
+  cpx<T>* g = X + (size_t)ls * CX * N * N * N + slab_base(slab);
+  const cpx<T>* yo = Y + ((size_t)ls * CX * N + slab) * CY * N * N;
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    md[k] = mdg[k];
+  }
+  __syncthreads();
+  constexpr int C1 = SC * L2, C2 = SC * L1;
+  constexpr int I1 = (C1 + NT - 1) / NT;
+  cpx<T> acc[I1][L1];
+#pragma unroll
+  for (int ii = 0; ii < I1; ++ii)
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) acc[ii][k1] = {T(0), T(0)};
+#pragma unroll 1
+  for (int cy = 0; cy < CY; ++cy) {
+    const cpx<T>* yc = yo + (size_t)cy * N * N;
+    // inverse step 2, items (zi, q1): ky = q1 + L1 q2
+    for (int it = tid; it < C2; it += NT) {
+      const int zi = it % SC, q1 = it / SC;
+      cpx<T> w[L2];
+#pragma unroll
+      for (int q2 = 0; q2 < L2; ++q2) w[q2] = yc[(size_t)(q1 + L1 * q2) * N + z0 + zi];
+      Dft<L2, 1, T>::run(w);
+#pragma unroll
+      for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q1]);
+#pragma unroll
+      for (int t = 0; t < L2; ++t) buf[(t + L2 * q1) * P + zi] = w[t];
+    }
+    __syncthreads();
+    // inverse step 1, items (zi, t): y = t + L2 k1, demodulate, sum over cy
+#pragma unroll
+    for (int ii = 0; ii < I1; ++ii) {
+      const int it = tid + ii * NT;
+      if (C1 % NT == 0 || it < C1) {
+        const int zi = it % SC, t = it / SC;
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = buf[(t + L2 * q1) * P + zi];
+        Dft<L1, 1, T>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1)
+          acc[ii][k1] = cadd(acc[ii][k1], cy ? cmulc(v[k1], md[t + L2 * k1]) : v[k1]);
+      }
+    }
+    __syncthreads();  // buf is rewritten by the next class
+  }
+  // write back the z-chunk of the slab (B1 has read it in an earlier launch)
+#pragma unroll
+  for (int ii = 0; ii < I1; ++ii) {
+    const int it = tid + ii * NT;
+    if (C1 % NT == 0 || it < C1) {
+      const int zi = it % SC, t = it / SC;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) g[slab_off<N, CX>(t + L2 * k1, z0 + zi)] = acc[ii][k1];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pass C: inverse x-transform of every slot of a pair tile for the rows
 // (y, z0..z0+ZB), then FP64 pair energies h^3 sum rho V (Eq. 5) and the
 // K psi sums (Eq. 3) of the tile's orbitals at the rows' points.
@@ -915,7 +1201,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 // 2n); k_slot_reduce sums each slot half's partials in a fixed order, so the
 // energies do not depend on block scheduling.
 // ---------------------------------------------------------------------------
-int energy_parts(int n) { return std::max(n * n / 16, 2 * n); }
+int energy_parts(int n) { return std::max(n * n / 8, 2 * n); }
 
 __global__ __launch_bounds__(256) void k_slot_reduce(const double* __restrict__ parts, int kparts,
                                                      int count, int nhalves,
@@ -1127,6 +1413,64 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
   });
 }
 
+// ---- split pass B (three launches) ------------------------------------------
+template <typename T, int N, int CX, int CY, int CZ>
+hipError_t launch_split_for(const Launch& L, cpx<T>* X, cpx<T>* Y, int nslots, bool energy_only,
+                            double* e_part, int slot0, const Tables& tb) {
+  constexpr int NT = 128;
+  auto* kt = static_cast<const T*>(tb.ktab);
+  auto* tw = static_cast<const cpx<T>*>(tb.tw);
+  auto* md = static_cast<const cpx<T>*>(tb.md);
+  dim3 grid(N / SC, CX * N, nslots);
+  hipLaunchKernelGGL((k_pass_b1<T, N, CX, CY, NT>), grid, dim3(NT), 0, L.stream, X, Y, tw, md);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (energy_only) {
+    hipLaunchKernelGGL((k_pass_b2<T, N, CX, CY, CZ, NT, true>), grid, dim3(NT), 0, L.stream, Y, kt,
+                       tw, md, e_part, slot0, energy_parts(N));
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_pass_b2<T, N, CX, CY, CZ, NT, false>), grid, dim3(NT), 0, L.stream, Y, kt,
+                     tw, md, e_part, slot0, energy_parts(N));
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_pass_b3<T, N, CX, CY, NT>), grid, dim3(NT), 0, L.stream, X, Y, tw, md);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pass_b_split(const Launch& L, void* X, void* Y, int nslots, bool energy_only,
+                               double* e_part, int slot0, const Tables& tb) {
+  if (nslots <= 0) return hipSuccess;
+  if (nslots > 65535) return hipErrorInvalidValue;
+  return dispatch_n(L.n, [&]<int N>() -> hipError_t {
+    auto* Xc = static_cast<cpx<T>*>(X);
+    auto* Yc = static_cast<cpx<T>*>(Y);
+    if (L.ncls == 2 && L.cy == 2 && L.cz == 2)
+      return launch_split_for<T, N, 2, 2, 2>(L, Xc, Yc, nslots, energy_only, e_part, slot0, tb);
+    if (L.ncls == 1 && L.cy == 1 && L.cz == 2)
+      return launch_split_for<T, N, 1, 1, 2>(L, Xc, Yc, nslots, energy_only, e_part, slot0, tb);
+    if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
+      return launch_split_for<T, N, 1, 1, 1>(L, Xc, Yc, nslots, energy_only, e_part, slot0, tb);
+    return hipErrorInvalidValue;
+  });
+}
+
+// Large FP32 slabs without the shared-y variant take the split pass B.
+bool pass_b_split(int precision, int n, int ncls, int cy, int cz) {
+  if (precision != EXX_PREC_FP32 || n < 96) return false;
+  bool sy = false;
+  (void)dispatch_n(n, [&]<int N>() -> hipError_t {
+    if (ncls == 2 && cy == 2 && cz == 2) sy = pass_b_share_y<float, N, 2, 2>();
+    else if (ncls == 1 && cy == 1 && cz == 2) sy = pass_b_share_y<float, N, 1, 2>();
+    return hipSuccess;
+  });
+  return !sy;
+}
+
+// Energy partials per slot half written by the split pass B (one per slab and ky-chunk).
+int split_energy_parts_used(int n, int ncls) { return ncls * n * (n / SC); }
+
 int pass_c_max_tile(int n) {
   switch (n) {
     case 16: return pass_c_tile<16>();
@@ -1179,6 +1523,8 @@ template hipError_t launch_pass_b<float>(const Launch&, void*, int, bool, double
                                          const Tables&, int);
 template hipError_t launch_pass_b<double>(const Launch&, void*, int, bool, double*, int,
                                           const Tables&, int);
+template hipError_t launch_pass_b_split<float>(const Launch&, void*, void*, int, bool, double*, int,
+                                               const Tables&);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
                                          const Slot*, const TilePair*, int, int, int, double*,
                                          double*, bool, bool, bool, int, const Tables&);

@@ -84,6 +84,13 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
                          bool pair_out, int tmax, const Tables& tb);
+// pass B in three launches through a scratch of ncls cy n^3 values per slot
+// (large slabs, FP32); used when pass_b_split() says so
+template <typename T>
+hipError_t launch_pass_b_split(const Launch& L, void* X, void* Y, int nslots, bool energy_only,
+                               double* e_part, int slot0, const Tables& tb);
+bool pass_b_split(int precision, int n, int ncls, int cy, int cz);
+int split_energy_parts_used(int n, int ncls);
 int energy_parts(int n);  // pair-energy partials per slot half (fused passes)
 hipError_t launch_slot_reduce(const double* parts, int kparts, int count, int nhalves,
                               double* e_slot, hipStream_t s);

@@ -113,3 +113,26 @@ def test_workspace_too_small_is_rejected():
     with pytest.raises(RuntimeError, match="CAPACITY"):
         big = torch.zeros((5, 16, 16, 16), dtype=torch.float64, device=dev)
         plan.compute(big, torch.ones(5, dtype=torch.float64, device=dev), "energy_kpsi")
+
+
+# Large slabs on the FP32 path take the three-launch pass B (y columns, z lines,
+# inverse y columns); the FP64 fused path stops at n = 96.
+SPLIT_CASES = [("free", 96, 3, 34, 0), ("free", 112, 2, 35, 0), ("surface", 112, 3, 36, 0),
+               ("periodic", 96, 3, 37, 0), ("free", 128, 2, 38, 0)]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=lambda c: f"{c[0]}{c[1]}_N{c[2]}")
+def test_fp32_split_pass_b_within_tolerance(case):
+    bc, n, N, seed, frac = case
+    say(f"[parity split] fp32 {bc} n={n} N={N} seed={seed}")
+    s, ref = oracle_result(bc, n, N, seed, frac)
+    E, K, P = run(s, "fp32")
+    assert abs(E - ref["E"]) / N < TOL_FP32_E_PER_ORB
+    assert kpsi_rel_err(K, ref["kpsi"]) < TOL_FP32_K
+    assert np.max(np.abs(P - ref["pair_e"])) <= 1e-6 * np.max(np.abs(ref["pair_e"]))
+    # the energy-only (Parseval) route through the split pass B
+    dev = torch.device("cuda", 0)
+    plan = exx.Plan(grid_of(s), "fp32", n_orb_max=N)
+    ex, _, _ = plan.compute(torch.from_numpy(s.psi).to(dev), torch.from_numpy(s.occ).to(dev), "energy")
+    torch.cuda.synchronize()
+    assert abs(ex.item() - ref["E"]) / N < TOL_FP32_E_PER_ORB
