@@ -748,13 +748,14 @@ __global__ __launch_bounds__(NT) void k_pass_b2(cpx<T>* __restrict__ Y, const T*
 #pragma unroll 1
   for (int cy = 0; cy < CY; ++cy) {
     cpx<T>* yc = yo + (size_t)cy * N * N;
-    // the lines' values, items (kyi, t): z = t + L2 k1, and their z-class sums
+    // the lines' values, items (kyi, t): z = t + L2 k1, and their z-class sums;
+    // t runs fastest across lanes, so global accesses cover runs of L2 z values
     cpx<T> vals[I1][L1], wacc[I1][L1];
 #pragma unroll
     for (int ii = 0; ii < I1; ++ii) {
       const int it = tid + ii * NT;
       if (C1 % NT == 0 || it < C1) {
-        const int kyi = it % SC, t = it / SC;
+        const int t = it % L2, kyi = it / L2;
 #pragma unroll
         for (int k1 = 0; k1 < L1; ++k1) {
           vals[ii][k1] = yc[(size_t)(k0 + kyi) * N + t + L2 * k1];
@@ -769,7 +770,7 @@ __global__ __launch_bounds__(NT) void k_pass_b2(cpx<T>* __restrict__ Y, const T*
       for (int ii = 0; ii < I1; ++ii) {
         const int it = tid + ii * NT;
         if (C1 % NT == 0 || it < C1) {
-          const int kyi = it % SC, t = it / SC;
+          const int t = it % L2, kyi = it / L2;
           cpx<T> v[L1];
 #pragma unroll
           for (int k1 = 0; k1 < L1; ++k1) v[k1] = cz ? cmul(vals[ii][k1], md[t + L2 * k1]) : vals[ii][k1];
@@ -821,7 +822,7 @@ __global__ __launch_bounds__(NT) void k_pass_b2(cpx<T>* __restrict__ Y, const T*
         for (int ii = 0; ii < I1; ++ii) {
           const int it = tid + ii * NT;
           if (C1 % NT == 0 || it < C1) {
-            const int kyi = it % SC, t = it / SC;
+            const int t = it % L2, kyi = it / L2;
             cpx<T> v[L1];
 #pragma unroll
             for (int q1 = 0; q1 < L1; ++q1) v[q1] = buf[(t + L2 * q1) * P + kyi];
@@ -839,7 +840,7 @@ __global__ __launch_bounds__(NT) void k_pass_b2(cpx<T>* __restrict__ Y, const T*
       for (int ii = 0; ii < I1; ++ii) {
         const int it = tid + ii * NT;
         if (C1 % NT == 0 || it < C1) {
-          const int kyi = it % SC, t = it / SC;
+          const int t = it % L2, kyi = it / L2;
 #pragma unroll
           for (int k1 = 0; k1 < L1; ++k1) yc[(size_t)(k0 + kyi) * N + t + L2 * k1] = wacc[ii][k1];
         }
