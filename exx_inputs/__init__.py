@@ -2,11 +2,11 @@
 
 Holds no exchange arithmetic; see ``generator`` for the grid convention.
 """
-from .generator import (FREE, PERIODIC, SURFACE, OrbitalRecipe, System, draw_system, loewdin,
+from .generator import (FREE, PERIODIC, SURFACE, WIRE, OrbitalRecipe, System, draw_system, loewdin,
                         make_system)
 from .workloads import BATCH, SINGLE, batch_recipes, pair_count, recipe, scaled, system
 
 __all__ = [
-    "FREE", "PERIODIC", "SURFACE", "OrbitalRecipe", "System", "draw_system", "loewdin", "make_system",
+    "FREE", "PERIODIC", "SURFACE", "WIRE", "OrbitalRecipe", "System", "draw_system", "loewdin", "make_system",
     "BATCH", "SINGLE", "batch_recipes", "pair_count", "recipe", "scaled", "system",
 ]

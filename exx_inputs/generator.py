@@ -24,6 +24,7 @@ import numpy as np
 PERIODIC = "periodic"
 FREE = "free"
 SURFACE = "surface"  # periodic in x and y, isolated along z
+WIRE = "wire"  # isolated in x and y, periodic along z
 
 
 @dataclass(frozen=True)
@@ -33,9 +34,10 @@ class OrbitalRecipe:
     n: grid points per axis; h: spacing (bohr); n_orb: number of orbitals;
     n_gauss: Gaussians per orbital; sigma: (lo, hi) of the uniform width draw;
     centres: "box" (uniform in [0, L)^3, minimum image -- periodic systems),
-    "middle" (uniform in [0.25 L, 0.75 L]^3 -- isolated systems) or "slab"
+    "middle" (uniform in [0.25 L, 0.75 L]^3 -- isolated systems), "slab"
     (x, y uniform in [0, L) with minimum image, z in [0.25 L, 0.75 L] --
-    surface systems);
+    surface systems) or "rod" (x, y in [0.25 L, 0.75 L], z uniform in [0, L)
+    with minimum image -- wire systems);
     ptype: multiply each Gaussian by a random p-type factor u.(r - A)/sigma;
     frac_last: number of trailing orbitals with occupation drawn U[0, 2];
     occ: occupation of the others.
@@ -73,7 +75,7 @@ def raw_gaussian_orbitals(rec: OrbitalRecipe, rng: np.random.Generator) -> np.nd
     n, h, L = rec.n, rec.h, rec.n * rec.h
     # per axis (x, y, z): periodic placement with minimum image, or confined
     periodic = {"box": (True, True, True), "middle": (False, False, False),
-                "slab": (True, True, False)}[rec.centres]
+                "slab": (True, True, False), "rod": (False, False, True)}[rec.centres]
     phi = np.zeros((rec.n_orb, n, n, n), dtype=np.float64)
     for i in range(rec.n_orb):
         for _ in range(rec.n_gauss):
@@ -163,5 +165,5 @@ class System:
 def make_system(rec: OrbitalRecipe, R: float | None = None) -> System:
     psi, occ = draw_system(rec)
     if R is None:
-        R = rec.n * rec.h if rec.bc in (FREE, SURFACE) else 0.0
+        R = rec.n * rec.h if rec.bc in (FREE, SURFACE, WIRE) else 0.0
     return System(rec, psi, occ, float(R))

@@ -8,7 +8,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .generator import FREE, PERIODIC, SURFACE, OrbitalRecipe, System, make_system
+from .generator import FREE, PERIODIC, SURFACE, WIRE, OrbitalRecipe, System, make_system
 
 H = 0.4  # grid spacing in bohr for every workload
 
@@ -32,6 +32,11 @@ def recipe(name: str) -> OrbitalRecipe:
         # zero padded, interaction cut at |z - z'| = L); 32 orbitals
         return OrbitalRecipe(n=64, h=H, n_orb=32, n_gauss=4, sigma=(0.6, 1.5),
                              centres="slab", bc=SURFACE, seed=1006)
+    if name == "wire64_n32":
+        # wire: isolated in x, y (64 -> 128 zero padded each, interaction cut at
+        # in-plane distance L), periodic along z (L = 25.6 bohr); 32 orbitals
+        return OrbitalRecipe(n=64, h=H, n_orb=32, n_gauss=4, sigma=(0.6, 1.5),
+                             centres="rod", bc=WIRE, seed=1007)
     if name == "free128_n256":
         # isolated, 128^3 grid zero-padded to 256^3, 256 orbitals, last 16 fractional
         return OrbitalRecipe(n=128, h=H, n_orb=256, n_gauss=4, sigma=(0.6, 1.5),
@@ -39,7 +44,8 @@ def recipe(name: str) -> OrbitalRecipe:
     raise KeyError(name)
 
 
-SINGLE = ("periodic32_n8", "free64_n32", "periodic96_n128", "free128_n256", "surface64_n32")
+SINGLE = ("periodic32_n8", "free64_n32", "periodic96_n128", "free128_n256", "surface64_n32",
+          "wire64_n32")
 BATCH = "batch16_free"
 
 

@@ -37,6 +37,13 @@ design notes):
       4 pi / G_z^2 [1 - cos(G_z R) - G_z R sin(G_z R)],   -2 pi R^2 at G = 0
   (the in-plane integral of 1/r diverges at G_par = 0; dropping its constant
   is the usual convention for a 2-D periodic array of charges);
+* wire (isolated in x and y, periodic along z): FFT grid 2n x 2n x n, zero
+  padding in x and y, the Coulomb interaction cut at the in-plane distance
+  rho = R (default L): with G_perp the in-plane and G_z the axial wave vector,
+      4 pi / G^2 [1 + R (G_perp J1(G_perp R) K0(|G_z| R) - |G_z| J0(G_perp R) K1(|G_z| R))]
+  for G_z != 0; for G_z = 0 the transform of the 2-D potential -2 ln(rho) on
+  rho < R (rho in bohr), 4 pi / G_perp^2 [1 - J0(G_perp R) - G_perp R J1(G_perp R) ln R],
+  and pi R^2 (1 - 2 ln R) at G = 0;
 * G = 2 pi k / (m h) with k folded to the symmetric range (k > m/2 -> k - m).
 
 Parity pins: see tests/test_oracle_*.py (closed forms for plane waves and
@@ -53,6 +60,7 @@ import scipy.fft as sfft
 PERIODIC = "periodic"
 FREE = "free"
 SURFACE = "surface"  # periodic x, y; isolated z
+WIRE = "wire"  # isolated x, y; periodic z
 SCREENED = "screened"  # periodic-style erfc(omega r)/r kernel (screened hybrids)
 
 _WORKERS = int(os.environ.get("EXX_ORACLE_WORKERS", "0")) or (os.cpu_count() or 1)
@@ -60,8 +68,8 @@ _WORKERS = int(os.environ.get("EXX_ORACLE_WORKERS", "0")) or (os.cpu_count() or 
 
 def fft_size(n: int, bc: str) -> int:
     """FFT grid points per axis: n for periodic, 2n (zero padded) for free."""
-    if bc == SURFACE:
-        raise ValueError("the surface grid is not cubic: use fft_shape")
+    if bc in (SURFACE, WIRE):
+        raise ValueError("the mixed-boundary grids are not cubic: use fft_shape")
     return 2 * n if bc == FREE else n
 
 
@@ -71,6 +79,8 @@ def fft_shape(n: int, bc: str) -> tuple:
         return (2 * n, 2 * n, 2 * n)
     if bc == SURFACE:
         return (2 * n, n, n)
+    if bc == WIRE:
+        return (n, 2 * n, 2 * n)
     return (n, n, n)
 
 
@@ -116,11 +126,34 @@ def surface_kernel(n: int, h: float, R: float | None = None) -> np.ndarray:
     return out
 
 
+def wire_kernel(n: int, h: float, R: float | None = None) -> np.ndarray:
+    """Coulomb kernel cut at in-plane distance R, periodic along z (2n x 2n x n grid)."""
+    from scipy import special
+    if R is None or R <= 0.0:
+        R = default_radius(n, h)
+    gz, gy, gx = wavevector_components(fft_shape(n, WIRE), h)
+    gp = np.sqrt(gx * gx + gy * gy) + 0.0 * gz  # in-plane |G|, full shape
+    az = np.abs(gz) + 0.0 * gp
+    G2 = gp * gp + az * az
+    out = np.empty_like(G2)
+    ax = az > 0.0
+    out[ax] = (4.0 * math.pi / G2[ax]) * (
+        1.0 + R * (gp[ax] * special.j1(gp[ax] * R) * special.k0(az[ax] * R)
+                   - az[ax] * special.j0(gp[ax] * R) * special.k1(az[ax] * R)))
+    plane = (~ax) & (gp > 0.0)
+    x = gp[plane] * R
+    out[plane] = (4.0 * math.pi / G2[plane]) * (1.0 - special.j0(x) - x * special.j1(x) * math.log(R))
+    out[(~ax) & (gp == 0.0)] = math.pi * R * R * (1.0 - 2.0 * math.log(R))
+    return out
+
+
 def kernel_hat(n: int, h: float, bc: str, R: float | None = None,
                omega: float = 0.0) -> np.ndarray:
     """Fourier-space Green's kernel on the FFT grid (real, even in G)."""
     if bc == SURFACE:
         return surface_kernel(n, h, R)
+    if bc == WIRE:
+        return wire_kernel(n, h, R)
     m = fft_size(n, bc)
     G2 = wavevector_sq(m, h)
     out = np.zeros_like(G2)

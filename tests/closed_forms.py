@@ -173,3 +173,47 @@ def slab_gaussian_self_energy(Q: float, c: float, L: float, kmax: int) -> float:
     Gn = G[G > 0]
     total = math.fsum(np.sort(_erfc(Gn * c) / Gn).tolist()) - 2.0 * c / math.sqrt(math.pi)
     return 2.0 * math.pi * Q * Q / (L * L) * total
+
+
+def _rice_mean(g, D: float, s: float) -> float:
+    """E[g(r)] for r = |D + u|, u a 2-D Gaussian of variance s^2 per axis (Rice law),
+    by adaptive quadrature of the Rice density (i0e keeps it finite)."""
+    from scipy import integrate
+    from scipy.special import i0e
+
+    def pdf(r):
+        return (r / (s * s)) * math.exp(-(r - D) ** 2 / (2.0 * s * s)) * i0e(r * D / (s * s))
+
+    hi = D + 12.0 * s
+    pts = [D] if D > 0 else None
+    val, _ = integrate.quad(lambda r: g(r) * pdf(r), 0.0, hi, points=pts, limit=400,
+                            epsabs=1e-14, epsrel=1e-12)
+    return val
+
+
+def wire_gaussian_interaction(Q1, P1, c1, Q2, P2, c2, L: float, kmax: int) -> float:
+    """int int Q1 N(P1,c1)(r) Q2 N(P2,c2)(r') v(r - r') for densities isolated in x, y
+    and periodic along z with period L, v = 1/|r| with the axial G = 0 term taken
+    as the 2-D potential -2 ln(rho) (rho in bohr).  Lattice sum over
+    G_z = 2 pi k / L, |k| <= kmax, with the in-plane average over the Rice law of
+    rho = |D + u| done by quadrature:
+
+      (Q1 Q2 / L) sum_{G_z} e^{-G_z^2 s^2 / 2} cos(G_z dz) E[k_{G_z}(rho)],
+      k_{G_z}(rho) = 2 K0(|G_z| rho) (G_z != 0),  -2 ln rho (G_z = 0),
+
+    s^2 = c1^2 + c2^2, dz and D the axial and in-plane offsets of the centres.
+    """
+    from scipy.special import k0
+    P1 = np.asarray(P1, float)
+    P2 = np.asarray(P2, float)
+    s = math.sqrt(c1 * c1 + c2 * c2)
+    dz = float(P1[2] - P2[2])
+    D = float(math.hypot(P1[0] - P2[0], P1[1] - P2[1]))
+    terms = [-2.0 * _rice_mean(lambda r: math.log(r) if r > 0 else 0.0, D, s)]
+    for k in range(1, kmax + 1):
+        G = 2.0 * math.pi * k / L
+        w = math.exp(-G * G * s * s / 2.0)
+        if w < 1e-30:
+            break
+        terms.append(2.0 * w * math.cos(G * dz) * _rice_mean(lambda r, G=G: 2.0 * k0(G * r), D, s))
+    return Q1 * Q2 / L * math.fsum(terms)
