@@ -34,7 +34,8 @@ FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 METRIC = "orbital-pair Poisson solves/s (E_x+Kψ) FP32-batched vs FP64, HBM GB/s"
 
 
-CLASSES = {"free": (2, 2, 2), "surface": (1, 1, 2), "periodic": (1, 1, 1)}  # per axis x, y, z
+CLASSES = {"free": (2, 2, 2), "surface": (1, 1, 2), "wire": (2, 2, 1),
+           "periodic": (1, 1, 1)}  # parity classes per axis x, y, z
 
 
 def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int) -> dict:
@@ -149,6 +150,8 @@ def workload_text(sysm, pairs: int) -> str:
     geom = {"free": f"free-BC {n}^3 grid padded to {2 * n}^3, h={h} bohr, R=L={L:g} bohr",
             "surface": f"surface (periodic x, y; isolated z) {n}^3 grid padded to {n}x{n}x{2 * n}, "
                        f"h={h} bohr, R=L={L:g} bohr",
+            "wire": f"wire (isolated x, y; periodic z) {n}^3 grid padded to {2 * n}x{2 * n}x{n}, "
+                    f"h={h} bohr, R=L={L:g} bohr",
             "periodic": f"periodic {n}^3 grid, h={h} bohr"}[sysm.bc]
     occ = "occupations 2" if float(sysm.occ.min()) == float(sysm.occ.max()) == 2.0 \
         else "occupations 2 with fractional tail"
@@ -310,7 +313,7 @@ def main(argv=None) -> int:
     pairs = pair_count(N)
     classes = CLASSES[sysm.bc]
     ncls = classes[0]
-    grid = exx.Grid(n=n, h=sysm.h, bc=sysm.bc, R=sysm.R if sysm.bc in ("free", "surface") else None)
+    grid = exx.Grid(n=n, h=sysm.h, bc=sysm.bc, R=sysm.R if sysm.bc != "periodic" else None)
     psi = torch.from_numpy(sysm.psi).to(dev)
     occ = torch.from_numpy(sysm.occ).to(dev)
     kpsi = torch.empty_like(psi)

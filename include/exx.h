@@ -56,8 +56,13 @@ extern "C" {
  *               4 pi / G^2 [1 + e^{-Gp R} (Gz / Gp sin(Gz R) - cos(Gz R))], Gp > 0,
  *               4 pi / Gz^2 [1 - cos(Gz R) - Gz R sin(Gz R)],  Gp = 0 (the in-plane
  *               G = 0 part is the transform of -2 pi |z|), -2 pi R^2 at G = 0,
- *             with Gp the in-plane and Gz the normal wave vector. */
-enum exx_bc { EXX_BC_PERIODIC = 0, EXX_BC_FREE = 1, EXX_BC_SURFACE = 2 };
+ *             with Gp the in-plane and Gz the normal wave vector;
+ *   WIRE    : isolated in x and y, periodic along z; zero padding to 2n in x and y,
+ *             Coulomb cut at in-plane distance rho = R:
+ *               4 pi / G^2 [1 + R (Gp J1(Gp R) K0(|Gz| R) - |Gz| J0(Gp R) K1(|Gz| R))], Gz != 0,
+ *               4 pi / Gp^2 [1 - J0(Gp R) - Gp R J1(Gp R) ln R],  Gz = 0 (the transform of
+ *               the 2-D potential -2 ln rho, rho in bohr), pi R^2 (1 - 2 ln R) at G = 0. */
+enum exx_bc { EXX_BC_PERIODIC = 0, EXX_BC_FREE = 1, EXX_BC_SURFACE = 2, EXX_BC_WIRE = 3 };
 
 /* Kernel of the pair Poisson problem.  COULOMB is 1/r (Eq. 4; truncated at R
  * for free boundaries).  SCREENED is erfc(omega r)/r, the short-range kernel of
@@ -100,8 +105,8 @@ typedef struct exx_grid {
   double hx, hy, hz; /* spacings in bohr, > 0 */
   int bc;            /* enum exx_bc */
   int kernel;        /* enum exx_kernel */
-  double R;          /* truncation radius (FREE: |r|, SURFACE: |z|); <= 0 selects the box
-                        length n h (along z for SURFACE) */
+  double R;          /* truncation radius (FREE: |r|, SURFACE: |z|, WIRE: in-plane
+                        distance); <= 0 selects the box length n h */
   double omega;      /* screening parameter for EXX_KERNEL_SCREENED (> 0) */
 } exx_grid;
 

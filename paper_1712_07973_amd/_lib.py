@@ -12,7 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libexx.so")
 
 # enums mirrored from include/exx.h
-BC_PERIODIC, BC_FREE, BC_SURFACE = 0, 1, 2
+BC_PERIODIC, BC_FREE, BC_SURFACE, BC_WIRE = 0, 1, 2, 3
 KERNEL_COULOMB, KERNEL_SCREENED = 0, 1
 PREC_FP32, PREC_FP64_PLAIN, PREC_FP64_FUSED = 0, 1, 2
 MODE_ENERGY, MODE_KPSI, MODE_ENERGY_KPSI = 1, 2, 3

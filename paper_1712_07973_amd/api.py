@@ -21,7 +21,8 @@ MODES = {"energy": L.MODE_ENERGY, "kpsi": L.MODE_KPSI, "energy_kpsi": L.MODE_ENE
 @dataclass(frozen=True)
 class Grid:
     """Cubic grid: n points per axis, spacing h (bohr), boundary 'periodic',
-    'free' (isolated) or 'surface' (periodic in x and y, isolated along z).
+    'free' (isolated), 'surface' (periodic in x and y, isolated along z) or
+    'wire' (isolated in x and y, periodic along z).
 
     R: truncation radius of the isolated directions (None: the box length n h).
     kernel: 'coulomb' (1/r) or 'screened' (erfc(omega r)/r, periodic only).
@@ -38,7 +39,8 @@ class Grid:
         g = L.ExxGrid()
         g.nx = g.ny = g.nz = int(self.n)
         g.hx = g.hy = g.hz = float(self.h)
-        g.bc = {"periodic": L.BC_PERIODIC, "free": L.BC_FREE, "surface": L.BC_SURFACE}[self.bc]
+        g.bc = {"periodic": L.BC_PERIODIC, "free": L.BC_FREE, "surface": L.BC_SURFACE,
+                "wire": L.BC_WIRE}[self.bc]
         g.kernel = {"coulomb": L.KERNEL_COULOMB, "screened": L.KERNEL_SCREENED}[self.kernel]
         g.R = float(self.R) if self.R else 0.0
         g.omega = float(self.omega)

@@ -69,6 +69,19 @@ double kernel_value(const exx_grid& g, double R, double Gp2, double Gz) {
     if (Gz != 0.0) return 4.0 * kPi / G2 * (1.0 - std::cos(Gz * R) - Gz * R * std::sin(Gz * R));
     return -2.0 * kPi * R * R;
   }
+  if (g.bc == EXX_BC_WIRE) {  // Coulomb cut at in-plane distance R, periodic along z
+    const double Gp = std::sqrt(Gp2), az = std::fabs(Gz);
+    if (az > 0.0)
+      return 4.0 * kPi / G2 *
+             (1.0 + R * (Gp * std::cyl_bessel_j(1.0, Gp * R) * std::cyl_bessel_k(0.0, az * R) -
+                         az * std::cyl_bessel_j(0.0, Gp * R) * std::cyl_bessel_k(1.0, az * R)));
+    if (Gp > 0.0) {
+      const double x = Gp * R;
+      return 4.0 * kPi / G2 *
+             (1.0 - std::cyl_bessel_j(0.0, x) - x * std::cyl_bessel_j(1.0, x) * std::log(R));
+    }
+    return kPi * R * R * (1.0 - 2.0 * std::log(R));
+  }
   if (G2 == 0.0) return 2.0 * kPi * R * R;
   double G = std::sqrt(G2);
   double s = std::sin(0.5 * G * R);
@@ -440,7 +453,8 @@ int validate_grid(const exx_grid* g, int precision) {
   if (!(g->hx > 0) || !(g->hy > 0) || !(g->hz > 0) || !std::isfinite(g->hx) || !std::isfinite(g->hy) ||
       !std::isfinite(g->hz))
     return fail(EXX_ERR_INVALID_ARG, "grid spacings must be positive and finite");
-  if (g->bc != EXX_BC_PERIODIC && g->bc != EXX_BC_FREE && g->bc != EXX_BC_SURFACE)
+  if (g->bc != EXX_BC_PERIODIC && g->bc != EXX_BC_FREE && g->bc != EXX_BC_SURFACE &&
+      g->bc != EXX_BC_WIRE)
     return fail(EXX_ERR_INVALID_ARG, "unknown boundary condition");
   if (g->kernel != EXX_KERNEL_COULOMB && g->kernel != EXX_KERNEL_SCREENED)
     return fail(EXX_ERR_INVALID_ARG, "unknown kernel");
@@ -492,15 +506,19 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
   p->grid = *grid;
   p->n = grid->nx;
   // parity classes per axis: 2 on zero-padded (isolated) axes
-  p->ncls = grid->bc == EXX_BC_FREE ? 2 : 1;
-  p->cy = grid->bc == EXX_BC_FREE ? 2 : 1;
-  p->cz = grid->bc == EXX_BC_PERIODIC ? 1 : 2;
+  const bool iso_xy = grid->bc == EXX_BC_FREE || grid->bc == EXX_BC_WIRE;
+  const bool iso_z = grid->bc == EXX_BC_FREE || grid->bc == EXX_BC_SURFACE;
+  p->ncls = iso_xy ? 2 : 1;
+  p->cy = iso_xy ? 2 : 1;
+  p->cz = iso_z ? 2 : 1;
   p->m = Dims{p->ncls * p->n, p->cy * p->n, p->cz * p->n};
   p->h3 = grid->hx * grid->hy * grid->hz;
   if (grid->R > 0)
     p->R = grid->R;
   else if (grid->bc == EXX_BC_SURFACE)
     p->R = p->n * grid->hz;
+  else if (grid->bc == EXX_BC_WIRE)
+    p->R = p->n * std::min(grid->hx, grid->hy);
   else
     p->R = p->n * std::min(grid->hx, std::min(grid->hy, grid->hz));
   p->precision = precision;

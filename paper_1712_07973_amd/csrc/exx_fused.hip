@@ -1374,8 +1374,8 @@ hipError_t launch_pass_b_cls(const Launch& L, cpx<T>* Xc, int nslots, bool energ
   return hipGetLastError();
 }
 
-// parity classes (x, y, z) of the three boundary conditions: free (2, 2, 2),
-// surface (1, 1, 2), periodic (1, 1, 1)
+// parity classes (x, y, z) of the boundary conditions: free (2, 2, 2),
+// surface (1, 1, 2), wire (2, 2, 1), periodic (1, 1, 1)
 template <typename T, int N, int CX, int CY, int CZ>
 hipError_t launch_pass_b_for(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
                              double* e_slot, int slot0, const Tables& tb, int slab_threads) {
@@ -1408,6 +1408,9 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
                                                 slab_threads);
       if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
         return launch_pass_b_for<T, N, 1, 1, 1>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
+                                                slab_threads);
+      if (L.ncls == 2 && L.cy == 2 && L.cz == 1)
+        return launch_pass_b_for<T, N, 2, 2, 1>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
                                                 slab_threads);
       return hipErrorInvalidValue;
     }

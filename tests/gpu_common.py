@@ -27,7 +27,8 @@ def small_system(bc: str, n: int, N: int, seed: int, frac: int = 0, ptype: bool 
                  h: float = 0.4):
     rec = OrbitalRecipe(n=n, h=h, n_orb=N, n_gauss=3,
                         sigma=(0.8, 1.6) if bc == "periodic" else (0.6, 1.5),
-                        centres={"periodic": "box", "free": "middle", "surface": "slab"}[bc],
+                        centres={"periodic": "box", "free": "middle", "surface": "slab",
+                                 "wire": "rod"}[bc],
                         bc=bc, ptype=ptype, frac_last=frac, seed=seed)
     return make_system(rec)
 
@@ -48,4 +49,4 @@ def kpsi_rel_err(a: np.ndarray, b: np.ndarray) -> float:
 
 def grid_of(s):
     import paper_1712_07973_amd as exx
-    return exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc in ("free", "surface") else None)
+    return exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc != "periodic" else None)

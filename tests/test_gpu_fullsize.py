@@ -44,7 +44,7 @@ def evaluate(s, precision):
     dev = torch.device("cuda", 0)
     psi = torch.from_numpy(s.psi).to(dev)
     occ = torch.from_numpy(s.occ).to(dev)
-    g = exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc in ("free", "surface") else None)
+    g = exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc != "periodic" else None)
     plan = exx.Plan(g, precision, n_orb_max=s.n_orb)
     pe = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=dev)
     ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)

@@ -2,7 +2,7 @@
 
 Sizes span several pair tiles with a ragged last tile (N not a multiple of
 the tile edge), an odd number of pairs (a half-filled packed slot), the three
-boundary conditions (periodic, free, surface) and the mixed radices 3, 5 and 7
+boundary conditions (periodic, free, surface, wire) and the mixed radices 3, 5 and 7
 of the supported grids.
 """
 import numpy as np
@@ -32,6 +32,10 @@ CASES = [
     ("surface", 64, 3, 31, 0),
     ("free", 80, 3, 32, 0),
     ("surface", 96, 3, 33, 0),
+    ("wire", 16, 4, 39, 1),
+    ("wire", 32, 7, 40, 0),
+    ("wire", 48, 3, 41, 0),
+    ("wire", 64, 3, 42, 0),
 ]
 
 
@@ -69,7 +73,7 @@ def test_fp32_path_within_tolerance(case):
     assert np.max(np.abs(P - ref["pair_e"])) <= 1e-6 * np.max(np.abs(ref["pair_e"]))
 
 
-@pytest.mark.parametrize("bc", ["free", "surface"])
+@pytest.mark.parametrize("bc", ["free", "surface", "wire"])
 @pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
 def test_energy_only_and_kpsi_only_modes(precision, bc):
     say(f"[modes] {precision} {bc}")
