@@ -34,6 +34,7 @@ PLANS = {
     "periodic96_n128": (False, 24, [3, 77], 2048),
     "free128_n256": (False, 12, [250], 2048),
     "surface64_n32": (True, 0, [0, 7, 31], 2048),
+    "wire64_n32": (True, 0, [0, 7, 31], 2048),
 }
 
 

@@ -95,6 +95,11 @@ def test_surface64_n32(precision):
     check("surface64_n32", precision)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
+def test_wire64_n32(precision):
+    check("wire64_n32", precision)
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64_fused"])
 def test_periodic96_n128(precision):
     check("periodic96_n128", precision)
