@@ -163,8 +163,8 @@ int exx_plan_set_tuning(exx_plan* plan, const exx_tuning* t);
 /* Times candidate tunings for n_orb orbitals with hipEvents on `stream` using
  * the caller's psi/occ/kpsi/ws buffers, keeps the fastest, and if cache_path is
  * non-NULL reads/writes a small text cache keyed by GPU arch, grid, boundary,
- * precision and n_orb.  budget_ms bounds the search (<= 0: default).
- * Synchronises the stream. */
+ * precision and n_orb.  budget_ms bounds the search's wall time: no new
+ * candidate starts once it is spent (<= 0: 20 s).  Synchronises the stream. */
 int exx_autotune(exx_plan* plan, const double* psi, const double* occ, int n_orb, double* kpsi,
                  void* ws, size_t ws_bytes, void* stream, int budget_ms, const char* cache_path);
 
@@ -180,10 +180,13 @@ typedef struct exx_system {
 typedef struct exx_batch exx_batch;
 
 /* A batch of n_systems independent systems (any mix of supported grids and
- * orbital counts, one precision).  All per-system work of one pass is issued
- * as a single launch over a merged work list; with use_graph != 0 the whole
- * evaluation is captured into a HIP graph on the first exx_batch_compute and
- * replayed afterwards (the system pointers must then stay the same). */
+ * orbital counts, one precision).  Each system keeps its own plan (kernels are
+ * specialised per grid size); the systems are issued on a few side streams
+ * forked from `stream` (largest first) so that they overlap, and joined back.
+ * With use_graph != 0 the whole evaluation is captured into one HIP graph on
+ * the first exx_batch_compute and replayed afterwards, one graph launch per
+ * call (the system pointers, mode, flags, workspace and stream must then stay
+ * the same; a change recaptures). */
 int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
                      int precision, int use_graph);
 void exx_batch_destroy(exx_batch* batch);

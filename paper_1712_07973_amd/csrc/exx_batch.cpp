@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -205,7 +206,12 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
 int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, double* kpsi,
                  void* ws, size_t ws_bytes, void* stream, int budget_ms, const char* cache_path) {
   if (!p || !psi || !occ || !kpsi) return EXX_ERR_INVALID_ARG;
-  (void)budget_ms;
+  const auto t_start = std::chrono::steady_clock::now();
+  const double budget = budget_ms > 0 ? (double)budget_ms : 20000.0;
+  auto spent = [&]() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+               .count() > budget;
+  };
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return EXX_ERR_HIP;
@@ -244,6 +250,7 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
     for (int bs : batches) {
      for (int sth : slab_threads) {
       for (int nst : streams) {
+      if (best_ms < 1e30f && spent()) continue;  // budget spent: keep the best so far
       exx_tuning cand = base;
       cand.tile = t;
       cand.batch_slots = bs;
