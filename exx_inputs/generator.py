@@ -1,8 +1,9 @@
 """Seeded synthetic orbitals for the exact-exchange workloads.
 
-This module only *draws inputs*: real orbitals on a uniform cubic grid built
-from random Gaussians and then Loewdin-orthonormalised, plus occupation
-numbers.  It contains none of the exchange arithmetic (no co-densities, no
+This module only *draws inputs*: real or complex orbitals on a uniform cubic
+grid built from random Gaussians (complex ones carry plane-wave phase
+factors and complex coefficients) and then Loewdin-orthonormalised, plus
+occupation numbers.  It contains none of the exchange arithmetic (no co-densities, no
 Poisson kernel, no FFT) so that both the FP64 oracle and the HIP path can use
 it without sharing any of the method's code.
 
@@ -40,7 +41,12 @@ class OrbitalRecipe:
     with minimum image -- wire systems);
     ptype: multiply each Gaussian by a random p-type factor u.(r - A)/sigma;
     frac_last: number of trailing orbitals with occupation drawn U[0, 2];
-    occ: occupation of the others.
+    occ: occupation of the others;
+    kmax: 0 for real orbitals; > 0 draws complex orbitals, each Gaussian term
+    times a complex coefficient of unit modulus and a phase exp(i k.(r - A)),
+    with k_a uniform in [-kmax, kmax] (bohr^-1) along an isolated axis and the
+    nearest multiple of 2 pi / L along a periodic one (so the orbital stays
+    periodic there).
     """
 
     n: int
@@ -54,6 +60,7 @@ class OrbitalRecipe:
     frac_last: int = 0
     occ: float = 2.0
     seed: int = 0
+    kmax: float = 0.0
 
 
 def _axis_displacement(n: int, h: float, a: float, periodic: bool) -> np.ndarray:
@@ -76,7 +83,8 @@ def raw_gaussian_orbitals(rec: OrbitalRecipe, rng: np.random.Generator) -> np.nd
     # per axis (x, y, z): periodic placement with minimum image, or confined
     periodic = {"box": (True, True, True), "middle": (False, False, False),
                 "slab": (True, True, False), "rod": (False, False, True)}[rec.centres]
-    phi = np.zeros((rec.n_orb, n, n, n), dtype=np.float64)
+    cplx = rec.kmax > 0.0
+    phi = np.zeros((rec.n_orb, n, n, n), dtype=np.complex128 if cplx else np.float64)
     for i in range(rec.n_orb):
         for _ in range(rec.n_gauss):
             coef = rng.uniform(-1.0, 1.0)
@@ -96,6 +104,14 @@ def raw_gaussian_orbitals(rec: OrbitalRecipe, rng: np.random.Generator) -> np.nd
                 )
             else:
                 term = np.einsum("z,y,x->zyx", gz, gy, gx)
+            if cplx:  # drawn after the real recipe's numbers, which stay unchanged
+                k = rng.uniform(-rec.kmax, rec.kmax, size=3)
+                for a in range(3):
+                    if periodic[a]:
+                        k[a] = 2.0 * np.pi / L * np.round(k[a] * L / (2.0 * np.pi))
+                px, py, pz = (np.exp(1j * k[a] * d) for a, d in enumerate((dx, dy, dz)))
+                term = term * np.einsum("z,y,x->zyx", pz, py, px)
+                coef = coef * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi))
             phi[i] += coef * term
     return phi
 
@@ -103,17 +119,19 @@ def raw_gaussian_orbitals(rec: OrbitalRecipe, rng: np.random.Generator) -> np.nd
 def loewdin(phi: np.ndarray, h: float, min_ratio: float = 1e-6):
     """Symmetric (Loewdin) orthonormalisation on the grid: psi = S^{-1/2} phi.
 
-    S_ij = h^3 sum_g phi_i(g) phi_j(g).  Returns (psi, eigenvalue ratio of S);
-    the ratio lets the caller redraw an ill-conditioned set.
+    S_ij = h^3 sum_g conj(phi_i(g)) phi_j(g) (Hermitian; real for real phi), and
+    psi_i = sum_k conj(S^{-1/2})_ik phi_k makes h^3 sum conj(psi_i) psi_j = delta_ij.
+    Returns (psi, eigenvalue ratio of S); the ratio lets the caller redraw an
+    ill-conditioned set.
     """
     N = phi.shape[0]
     flat = phi.reshape(N, -1)
-    S = (h ** 3) * (flat @ flat.T)
+    S = (h ** 3) * (np.conj(flat) @ flat.T)
     w, U = np.linalg.eigh(S)
     ratio = float(w.min() / w.max())
     if w.min() <= 0.0 or ratio < min_ratio:
         return None, ratio
-    C = (U * (1.0 / np.sqrt(w))) @ U.T
+    C = np.conj((U * (1.0 / np.sqrt(w))) @ np.conj(U).T)
     psi = (C @ flat).reshape(phi.shape)
     return np.ascontiguousarray(psi), ratio
 
@@ -138,7 +156,8 @@ def draw_system(rec: OrbitalRecipe, max_tries: int = 20):
 
 @dataclass
 class System:
-    """One drawn system: orbitals psi [N][n][n][n] (FP64) and occupations [N]."""
+    """One drawn system: orbitals psi [N][n][n][n] (FP64, complex128 when the
+    recipe's kmax > 0) and occupations [N]."""
 
     recipe: OrbitalRecipe
     psi: np.ndarray

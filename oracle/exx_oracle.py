@@ -8,14 +8,15 @@ time, with no packing, pruning, tiling or batching.
 
 What it computes (Ratcliff et al., arXiv:1712.07973, Section 2):
 
-* co-density of a pair, rho_ij(r) = psi_i(r) psi_j(r) for real orbitals
-  (Eq. 8; Eq. 2 defines it with a complex conjugate that is void here);
+* co-density of a pair, rho_ij(r) = psi_j*(r) psi_i(r) (Eq. 2; Eq. 8 writes the
+  real-orbital case psi_i psi_j); real and complex orbitals are accepted;
 * pair potential V_ij, the solution of lap V = -4 pi rho_ij (Eq. 4),
   obtained by a discrete convolution with a Green's kernel evaluated through
   FFTs with zero padding for isolated systems (Section 2.1.2);
-* E_x = -1/2 sum_{i,j} f_i f_j  integral rho_ij V_ij  (Eq. 5, one spin channel);
+* E_x = -1/2 sum_{i,j} f_i f_j  integral rho_ij* V_ij  (Eqs. 2 and 5, one spin
+  channel; real for any orbitals since V_ij = K * rho_ij with a real even K);
 * the Fock action, (K psi)_i = sum_j f_j V_ij psi_j, which is minus the
-  operator D_X of Eq. 3.
+  operator D_X of Eq. 3; V_ji = conj(V_ij).
 
 Discrete readings (the paper gives none of these; each is listed in the
 design notes):
@@ -194,7 +195,7 @@ def solve_poisson(rho: np.ndarray, h: float, bc: str, R: float | None = None,
                   omega: float = 0.0, khat: np.ndarray | None = None) -> np.ndarray:
     """V with lap V = -4 pi rho (Eq. 4) by FFT convolution with the kernel.
 
-    V = crop( IFFT( K^ . FFT( embed(rho) ) ) ); rho is real so V is real.
+    V = crop( IFFT( K^ . FFT( embed(rho) ) ) ); V is real for a real rho.
     """
     n = rho.shape[0]
     shape = fft_shape(n, bc)
@@ -203,17 +204,18 @@ def solve_poisson(rho: np.ndarray, h: float, bc: str, R: float | None = None,
     F = sfft.fftn(embed(rho, shape), workers=_WORKERS)
     V = sfft.ifftn(khat * F, workers=_WORKERS)
     V = V[:n, :n, :n]
-    return np.ascontiguousarray(V.real)
+    return np.ascontiguousarray(V if np.iscomplexobj(rho) else V.real)
 
 
 def co_density(psi_i: np.ndarray, psi_j: np.ndarray) -> np.ndarray:
-    """rho_ij = psi_i * psi_j (Eq. 8) for real orbitals."""
-    return psi_i * psi_j
+    """rho_ij = conj(psi_j) psi_i (Eq. 2); psi_i psi_j (Eq. 8) for real orbitals."""
+    return np.conj(psi_j) * psi_i if np.iscomplexobj(psi_j) else psi_i * psi_j
 
 
 def pair_energy(rho: np.ndarray, V: np.ndarray, h: float) -> float:
-    """integral rho V ~ h^3 sum_g rho(g) V(g), summed with math.fsum."""
-    return (h ** 3) * math.fsum((rho * V).ravel().tolist())
+    """integral conj(rho) V ~ h^3 sum_g Re(conj(rho(g)) V(g)), summed with math.fsum."""
+    prod = (np.conj(rho) * V).real if np.iscomplexobj(rho) or np.iscomplexobj(V) else rho * V
+    return (h ** 3) * math.fsum(prod.ravel().tolist())
 
 
 def exx(psi: np.ndarray, occ: np.ndarray, h: float, bc: str, R: float | None = None,
@@ -241,13 +243,14 @@ def exx(psi: np.ndarray, occ: np.ndarray, h: float, bc: str, R: float | None = N
             if want_kpsi:
                 kpsi[i] += occ[j] * V * psi[j]
                 if symmetric and j != i:
-                    kpsi[j] += occ[i] * V * psi[i]
+                    kpsi[j] += occ[i] * np.conj(V) * psi[i]  # V_ji = conj(V_ij)
     E = -0.5 * math.fsum((occ[:, None] * occ[None, :] * e).ravel().tolist())
     return {"E": E, "kpsi": kpsi, "pair_e": e}
 
 
 def exx_grad_psi(kpsi: np.ndarray, occ: np.ndarray, h: float) -> np.ndarray:
-    """dE_x / dpsi_k(g) = -2 f_k h^3 (K psi)_k(g) for the grid function."""
+    """dE_x / dpsi_k(g) = -2 f_k h^3 (K psi)_k(g) for the grid function (for complex
+    orbitals the gradient with respect to (Re psi, Im psi) read as one complex number)."""
     return -2.0 * (h ** 3) * occ[:, None, None, None] * kpsi
 
 
@@ -271,7 +274,7 @@ def kpsi_rows(psi: np.ndarray, occ: np.ndarray, rows, h: float, bc: str,
               R: float | None = None, omega: float = 0.0) -> np.ndarray:
     """(K psi)_i for the listed orbitals only (N solves per orbital)."""
     khat = kernel_hat(psi.shape[1], h, bc, R, omega)
-    out = np.zeros((len(rows),) + psi.shape[1:])
+    out = np.zeros((len(rows),) + psi.shape[1:], dtype=psi.dtype)
     for r, i in enumerate(rows):
         for j in range(psi.shape[0]):
             V = solve_poisson(co_density(psi[i], psi[j]), h, bc, khat=khat)
@@ -305,7 +308,7 @@ def brute_force_potential(rho: np.ndarray, h: float, bc: str, R: float | None = 
     n = rho.shape[0]
     mz, my, mx = fft_shape(n, bc)
     K = realspace_kernel(n, h, bc, R, omega)
-    V = np.zeros((n, n, n))
+    V = np.zeros((n, n, n), dtype=np.result_type(rho.dtype, K.dtype))
     src = np.argwhere(np.ones((n, n, n), dtype=bool))
     for (a, b, c) in src:
         w = rho[a, b, c]

@@ -217,3 +217,21 @@ def wire_gaussian_interaction(Q1, P1, c1, Q2, P2, c2, L: float, kmax: int) -> fl
             break
         terms.append(2.0 * w * math.cos(G * dz) * _rice_mean(lambda r, G=G: 2.0 * k0(G * r), D, s))
     return Q1 * Q2 / L * math.fsum(terms)
+
+
+def modulated_gaussian_self_energy(Q: float, c: float, kappa: float) -> float:
+    """Free-space  int int conj(rho(r)) rho(r') / |r - r'|  for the complex
+    density rho = exp(i kappa.r) Q N(P, c).
+
+    In Fourier space |rho^(q)|^2 = Q^2 exp(-c^2 |q - kappa|^2), so the energy
+    is Q^2 / (2 pi^2) int exp(-c^2 |q - kappa|^2) / q^2 d^3q; the angular
+    integral leaves (2 pi / (c^2 kappa)) int_0^inf exp(-c^2 (q^2 + kappa^2))
+    sinh(2 c^2 q kappa) / q dq, which is sqrt(pi) D(c kappa) with D Dawson's
+    integral.  Result: Q^2 D(c kappa) / (sqrt(pi) c^2 kappa), tending to
+    Q^2 / (c sqrt(pi)) as kappa -> 0.
+    """
+    from scipy.special import dawsn
+
+    if kappa < 1e-12:
+        return Q * Q / (c * math.sqrt(math.pi))
+    return Q * Q * float(dawsn(c * kappa)) / (math.sqrt(math.pi) * c * c * kappa)
