@@ -1,13 +1,18 @@
 /*
  * exx.h -- C ABI of the MI355X exact-exchange library (libexx.so).
  *
- * The library evaluates, for one spin channel of real orbitals psi_i on a
- * uniform cubic grid with occupations f_i,
+ * The library evaluates, for one spin channel of real (or, with
+ * EXX_PLAN_COMPLEX, complex) orbitals psi_i on a uniform cubic grid with
+ * occupations f_i,
  *
- *   rho_ij(r) = psi_i(r) psi_j(r)                         (co-density, Eq. 8)
+ *   rho_ij(r) = conj(psi_j(r)) psi_i(r)          (co-density, Eq. 2; Eq. 8 for real psi)
  *   V_ij      = solution of lap V = -4 pi rho_ij         (pair potential, Eq. 4)
- *   E_x       = -1/2 sum_{i,j} f_i f_j h^3 sum_r rho_ij V_ij          (Eq. 5)
+ *   E_x       = -1/2 sum_{i,j} f_i f_j h^3 sum_r Re(conj(rho_ij) V_ij)     (Eq. 5)
  *   (K psi)_i = sum_j f_j V_ij psi_j         (minus the Fock action D_X, Eq. 3)
+ *
+ * (V_ji = conj(V_ij), so the sum over unordered pairs covers every term.)
+ * A spin-polarized system is two calls (or a batch of two systems), one per
+ * spin channel with its own orbitals and occupations f_i,sigma (Eq. 2).
  *
  * following Ratcliff et al., arXiv:1712.07973, Section 2 (the pair-sum
  * scheme with one Poisson solve per unordered pair, N(N+1)/2 solves) and
@@ -18,6 +23,8 @@
  *   - grid point (ix,iy,iz), 0 <= i < n, sits at r = (hx ix, hy iy, hz iz);
  *   - psi and K psi are FP64, C-contiguous [n_orb][n][n][n] with x fastest,
  *     in DEVICE memory, 16-byte aligned;  occ is FP64 [n_orb] in device memory;
+ *     with EXX_PLAN_COMPLEX every psi and K psi value is an interleaved (re, im)
+ *     pair of FP64, [n_orb][n][n][n][2] (C99 double complex / complex128);
  *   - periodic boundary: FFT grid n^3, kernel 4 pi / |G|^2 with G = 0 dropped;
  *   - free boundary: FFT grid (2n)^3 with the data in the first octant, kernel
  *     4 pi (1 - cos |G| R) / |G|^2 (value 2 pi R^2 at G = 0), potential cropped
@@ -86,6 +93,13 @@ enum exx_mode { EXX_MODE_ENERGY = 1, EXX_MODE_KPSI = 2, EXX_MODE_ENERGY_KPSI = 3
 /* Flags of exx_compute / exx_batch_compute. */
 #define EXX_FLAG_ACCUMULATE 1u /* add into kpsi instead of overwriting it */
 
+/* Flags of exx_plan_create.  COMPLEX: complex orbitals (Eq. 2 with the
+ * conjugate): psi and K psi hold interleaved (re, im) FP64 pairs; every pair
+ * i <= j is one complex transform (the fused paths cannot pack two pairs per
+ * transform, so a complex evaluation costs twice the transforms of a real one);
+ * pair energies stay real. */
+#define EXX_PLAN_COMPLEX 1u
+
 /* Error codes. */
 enum exx_status {
   EXX_OK = 0,
@@ -115,8 +129,8 @@ typedef struct exx_plan exx_plan;
 /* Creates a plan for one grid and precision on the current HIP device: FFT
  * twiddles (computed in FP64 on the host, rounded once), the Green's kernel
  * table (FP64 on the host), and the default pair-tile schedule.  n_orb_max
- * bounds every later n_orb.  flags: reserved, pass 0.  Allocates device
- * memory; synchronous. */
+ * bounds every later n_orb.  flags: 0 (real orbitals) or EXX_PLAN_COMPLEX;
+ * other bits give EXX_ERR_INVALID_ARG.  Allocates device memory; synchronous. */
 int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_orb_max,
                     unsigned flags);
 void exx_plan_destroy(exx_plan* plan);
@@ -130,12 +144,13 @@ int exx_plan_prepare(exx_plan* plan, int n_orb);
 int exx_workspace_bytes(const exx_plan* plan, int n_orb, size_t* bytes);
 
 /* Evaluates the exchange for n_orb orbitals.
- *   psi    [n_orb][n][n][n] FP64, device;  occ [n_orb] FP64, device (f_i >= 0);
+ *   psi    [n_orb][n][n][n] FP64 (complex plan: (re, im) pairs), device;
+ *          occ [n_orb] FP64, device (f_i >= 0);
  *   mode   enum exx_mode;  flags EXX_FLAG_*;
  *   ex_out device FP64 scalar receiving E_x (Hartree); required if mode has ENERGY;
- *   kpsi   device FP64 [n_orb][n][n][n] receiving (K psi)_i; required if mode has KPSI;
- *   pair_e device FP64 [n_orb][n_orb] receiving e_ij = h^3 sum_r rho_ij V_ij
- *          (symmetric, both triangles written), or NULL;
+ *   kpsi   device FP64 like psi receiving (K psi)_i; required if mode has KPSI;
+ *   pair_e device FP64 [n_orb][n_orb] receiving e_ij = h^3 sum_r Re(conj(rho_ij) V_ij)
+ *          (real and symmetric, both triangles written), or NULL;
  *   ws     device workspace of ws_bytes >= exx_workspace_bytes(), 256-byte aligned;
  *   stream hipStream_t or NULL.
  * Outputs are complete when the stream reaches the end of the call. */
@@ -179,8 +194,9 @@ typedef struct exx_system {
 
 typedef struct exx_batch exx_batch;
 
-/* A batch of n_systems independent systems (any mix of supported grids and
- * orbital counts, one precision).  Each system keeps its own plan (kernels are
+/* A batch of n_systems independent systems of real orbitals (any mix of
+ * supported grids and orbital counts, one precision; e.g. the two spin
+ * channels of one system).  Each system keeps its own plan (kernels are
  * specialised per grid size); the systems are issued on a few side streams
  * forked from `stream` (largest first) so that they overlap, and joined back.
  * With use_graph != 0 the whole evaluation is captured into one HIP graph on

@@ -3,7 +3,8 @@
 PyTorch provides device memory (CUDA/HIP tensors) and the current stream;
 every step of the exchange evaluation runs in the library's HIP kernels.
 Arrays follow the library layout: psi is float64 ``[N, n, n, n]`` (x
-fastest) on a GPU, occ is float64 ``[N]`` on the same GPU.
+fastest) on a GPU -- complex128 for a plan made with ``complex_orbitals`` --
+and occ is float64 ``[N]`` on the same GPU.
 """
 from __future__ import annotations
 
@@ -59,11 +60,11 @@ def _ptr(t: torch.Tensor | None) -> int | None:
     return None if t is None else t.data_ptr()
 
 
-def _check_tensor(name: str, t: torch.Tensor, shape, device=None):
+def _check_tensor(name: str, t: torch.Tensor, shape, device=None, dtype=torch.float64):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch.Tensor")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_cuda:
         raise ValueError(f"{name} must live on a GPU (the library has no CPU path)")
     if device is not None and t.device != device:
@@ -75,12 +76,17 @@ def _check_tensor(name: str, t: torch.Tensor, shape, device=None):
 
 
 class Plan:
-    """An exx_plan for one grid and precision on the current GPU."""
+    """An exx_plan for one grid and precision on the current GPU.
+
+    complex_orbitals: psi and K psi are complex128 (rho_ij = conj(psi_j) psi_i).
+    """
 
     def __init__(self, grid: Grid, precision: str = "fp32", n_orb_max: int = 1024,
-                 device: torch.device | int | None = None):
+                 device: torch.device | int | None = None, complex_orbitals: bool = False):
         self.grid = grid
         self.precision = precision
+        self.complex_orbitals = bool(complex_orbitals)
+        self.dtype = torch.complex128 if self.complex_orbitals else torch.float64
         self.n_orb_max = int(n_orb_max)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else
                                    (device if isinstance(device, int) else device.index))
@@ -88,7 +94,9 @@ class Plan:
         g = grid.to_c()
         with torch.cuda.device(self.device):
             L.check(L.lib().exx_plan_create(C.byref(h), C.byref(g), PRECISIONS[precision],
-                                            self.n_orb_max, 0), "exx_plan_create")
+                                            self.n_orb_max,
+                                            L.PLAN_COMPLEX if self.complex_orbitals else 0),
+                    "exx_plan_create")
         self._h = h
         self._ws: torch.Tensor | None = None
 
@@ -158,7 +166,7 @@ class Plan:
         """Runs exx_compute on the current stream; returns (ex_out, kpsi, pair_e)."""
         n = self.grid.n
         N = int(psi.shape[0])
-        _check_tensor("psi", psi, (N, n, n, n), self.device)
+        _check_tensor("psi", psi, (N, n, n, n), self.device, self.dtype)
         _check_tensor("occ", occ, (N,), self.device)
         m = MODES[mode]
         if m & L.MODE_ENERGY and ex_out is None:
@@ -166,7 +174,7 @@ class Plan:
         if m & L.MODE_KPSI and kpsi is None:
             kpsi = torch.empty_like(psi)
         if kpsi is not None:
-            _check_tensor("kpsi", kpsi, (N, n, n, n), self.device)
+            _check_tensor("kpsi", kpsi, (N, n, n, n), self.device, self.dtype)
         if pair_e is not None:
             _check_tensor("pair_e", pair_e, (N, N), self.device)
         ws = workspace if workspace is not None else self.workspace(N)
@@ -199,19 +207,22 @@ class Plan:
 _PLANS: dict = {}
 
 
-def get_plan(grid: Grid, precision: str, n_orb: int, device: torch.device) -> Plan:
-    key = (grid, precision, device.index)
+def get_plan(grid: Grid, precision: str, n_orb: int, device: torch.device,
+             complex_orbitals: bool = False) -> Plan:
+    key = (grid, precision, device.index, bool(complex_orbitals))
     p = _PLANS.get(key)
     if p is None or p.n_orb_max < n_orb:
-        p = Plan(grid, precision, max(n_orb, 64), device)
+        p = Plan(grid, precision, max(n_orb, 64), device, complex_orbitals)
         _PLANS[key] = p
     return p
 
 
 def energy_and_kpsi(psi: torch.Tensor, occ: torch.Tensor, grid: Grid, precision: str = "fp32",
                     pair_energies: bool = False):
-    """E_x (0-dim float64 tensor), K psi (like psi) and optionally e_ij [N, N]."""
-    plan = get_plan(grid, precision, psi.shape[0], psi.device)
+    """E_x (0-dim float64 tensor), K psi (like psi) and optionally e_ij [N, N].
+
+    psi may be float64 or complex128 (complex orbitals)."""
+    plan = get_plan(grid, precision, psi.shape[0], psi.device, psi.is_complex())
     pe = torch.empty((psi.shape[0], psi.shape[0]), dtype=torch.float64,
                      device=psi.device) if pair_energies else None
     ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)
@@ -221,7 +232,7 @@ def energy_and_kpsi(psi: torch.Tensor, occ: torch.Tensor, grid: Grid, precision:
 def exchange_energy(psi: torch.Tensor, occ: torch.Tensor, grid: Grid,
                     precision: str = "fp32") -> torch.Tensor:
     """E_x alone (Parseval route: one forward transform per pair)."""
-    plan = get_plan(grid, precision, psi.shape[0], psi.device)
+    plan = get_plan(grid, precision, psi.shape[0], psi.device, psi.is_complex())
     ex, _, _ = plan.compute(psi, occ, "energy")
     return ex
 

@@ -8,8 +8,11 @@ returns the exact gradient of the grid function,
     dE_x / df_k      = -sum_j f_j e_kj,
 
 where (K psi)_k = sum_j f_j V_kj psi_j is minus the Fock action of Eq. 3 of
-arXiv:1712.07973 and e_kj the pair energies (Eq. 5).  E_x is a homogeneous
-quartic in psi and quadratic in f, which the tests use.
+arXiv:1712.07973 and e_kj the pair energies (Eq. 5).  For complex orbitals
+(complex128 psi) the first line is the gradient with respect to Re psi plus i
+times the one with respect to Im psi, which is PyTorch's convention for a real
+function of complex inputs.  E_x is a homogeneous quartic in psi and quadratic
+in f, which the tests use.
 """
 from __future__ import annotations
 
@@ -23,7 +26,7 @@ class ExchangeEnergy(torch.autograd.Function):
     def forward(ctx, psi: torch.Tensor, occ: torch.Tensor, grid: Grid, precision: str):
         psi_c = psi.detach().contiguous()
         occ_c = occ.detach().contiguous()
-        plan = get_plan(grid, precision, psi_c.shape[0], psi_c.device)
+        plan = get_plan(grid, precision, psi_c.shape[0], psi_c.device, psi_c.is_complex())
         ex, _, _ = plan.compute(psi_c, occ_c, "energy")
         ctx.save_for_backward(psi_c, occ_c)
         ctx.grid = grid
@@ -34,7 +37,7 @@ class ExchangeEnergy(torch.autograd.Function):
     def backward(ctx, g: torch.Tensor):
         psi, occ = ctx.saved_tensors
         grid, precision = ctx.grid, ctx.precision
-        plan = get_plan(grid, precision, psi.shape[0], psi.device)
+        plan = get_plan(grid, precision, psi.shape[0], psi.device, psi.is_complex())
         need_psi, need_occ = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         gpsi = gocc = None
         N = psi.shape[0]

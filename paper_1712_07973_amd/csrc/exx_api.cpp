@@ -134,8 +134,10 @@ size_t slot_bytes(const exx_plan* p) {
   return (size_t)p->ncls * p->n * p->n * p->n * c;
 }
 
+int max_tile(const exx_plan* p) { return pass_c_max_tile(p->precision, p->n, p->cplx); }
+
 void default_tuning(exx_plan* p) {
-  p->tuning.tile = pass_c_max_tile(p->n);
+  p->tuning.tile = max_tile(p);
   const size_t budget = (size_t)4 << 30;  // bytes of spectrum workspace per launch chunk
   size_t per = slot_bytes(p);
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
@@ -143,9 +145,13 @@ void default_tuning(exx_plan* p) {
   p->tuning.streams = 1;
 }
 
+int schedule_tile(const exx_plan* p) {
+  return is_plain(p) ? 0 : std::max(1, std::min(p->tuning.tile, max_tile(p)));
+}
+
 void build_schedule(const exx_plan* p, int N, Schedule& s) {
-  const int T = is_plain(p) ? 0 : std::max(1, std::min(p->tuning.tile, pass_c_max_tile(p->n)));
-  build_schedule_host(N, T, p->tuning.batch_slots, !is_plain(p), s);
+  const int packing = is_plain(p) ? kPlain : (p->cplx ? kTiled : kPacked);
+  build_schedule_host(N, schedule_tile(p), p->tuning.batch_slots, packing, s);
 }
 
 int cap_slots(const exx_plan* p, const Schedule& s) {
@@ -168,7 +174,8 @@ WsLayout layout(const exx_plan* p, const Schedule& s) {
   WsLayout w;
   size_t off = 0;
   w.psi32 = off;
-  if (is_fp32(p)) off += align_up((size_t)s.n_orb * p->n * p->n * p->n * sizeof(float), 256);
+  if (is_fp32(p))
+    off += align_up((size_t)s.n_orb * p->n * p->n * p->n * sizeof(float) * (p->cplx ? 2 : 1), 256);
   w.e_slot = off;
   off += align_up(2 * s.slots.size() * sizeof(double), 256);
   w.e_part = off;
@@ -189,7 +196,7 @@ WsLayout layout(const exx_plan* p, const Schedule& s) {
 int get_schedule(exx_plan* p, int N, Schedule** out, bool allow_build) {
   auto it = p->schedules.find(N);
   if (it != p->schedules.end() &&
-      it->second.tile == (is_plain(p) ? 0 : std::max(1, std::min(p->tuning.tile, pass_c_max_tile(p->n)))) &&
+      it->second.tile == schedule_tile(p) &&
       it->second.batch_slots == p->tuning.batch_slots) {
     *out = &it->second;
     return EXX_OK;
@@ -269,7 +276,8 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   const bool want_k = (mode & EXX_MODE_KPSI) != 0;
   const bool want_e = (mode & EXX_MODE_ENERGY) != 0 || pair_e != nullptr;
   const bool parseval = (mode == EXX_MODE_ENERGY) && pair_e == nullptr;
-  const size_t n3 = (size_t)p->n * p->n * p->n;
+  // values per orbital: n^3 doubles, or n^3 (re, im) pairs for complex orbitals
+  const size_t n3 = (size_t)p->n * p->n * p->n * (p->cplx ? 2 : 1);
   const T* psiT;
   if constexpr (sizeof(T) == 4) {
     float* p32 = reinterpret_cast<float*>(ws + w.psi32);
@@ -290,7 +298,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     EXX_PROF(EXX_PASS_ZERO);
     if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
   }
-  Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st};
+  Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st, p->cplx ? 1 : 0};
   // pass B over ns slots from slot s0 (spectra at Xs) on the stream of Lb: one
   // launch, or the split form in groups of w.split_slots
   auto pass_b = [&](const Launch& Lb, char* Xs, int s0, int ns) -> int {
@@ -407,7 +415,7 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
               double* pair_e, char* ws, hipStream_t st) {
   const bool want_k = (mode & EXX_MODE_KPSI) != 0;
   const bool want_e = (mode & EXX_MODE_ENERGY) != 0 || pair_e != nullptr;
-  const size_t n3 = (size_t)p->n * p->n * p->n;
+  const size_t n3 = (size_t)p->n * p->n * p->n * (p->cplx ? 2 : 1);  // doubles per orbital
   double* e_slot = reinterpret_cast<double*>(ws + w.e_slot);
   void* Z = ws + w.X;
   {
@@ -419,7 +427,7 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     const int np = c.s1 - c.s0;
     {
       EXX_PROF(EXX_PASS_PLAIN_OTHER);
-      EXX_HIP(plain_build(psi, s.d_slots, c.s0, np, p->n, p->m, Z, st));
+      EXX_HIP(plain_build(psi, s.d_slots, c.s0, np, p->n, p->m, Z, p->cplx, st));
     }
     for (int a = 0; a < 3; ++a) {
       EXX_PROF(EXX_PASS_PLAIN_FFT);
@@ -436,7 +444,7 @@ int run_plain(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     {
       EXX_PROF(EXX_PASS_PLAIN_OTHER);
       EXX_HIP(plain_reduce(Z, psi, occ, s.d_slots, c.s0, np, p->n, p->m, p->h3, kpsi, e_slot, want_k,
-                           want_e, st));
+                           want_e, p->cplx, st));
     }
   }
   if (want_e) {
@@ -495,9 +503,9 @@ const char* exx_error_string(int code) {
 
 int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_orb_max,
                     unsigned flags) {
-  (void)flags;
   if (!out) return fail(EXX_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  if ((flags & ~EXX_PLAN_COMPLEX) != 0) return fail(EXX_ERR_INVALID_ARG, "unknown plan flags");
   int rc = validate_grid(grid, precision);
   if (rc) return rc;
   if (n_orb_max <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb_max must be positive");
@@ -522,6 +530,7 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
   else
     p->R = p->n * std::min(grid->hx, std::min(grid->hy, grid->hz));
   p->precision = precision;
+  p->cplx = (flags & EXX_PLAN_COMPLEX) != 0;
   p->n_orb_max = n_orb_max;
   default_tuning(p);
   hipError_t e = hipGetDevice(&p->device);

@@ -96,8 +96,10 @@ __device__ __forceinline__ T sqrt_weight(const double* occ, int i, int j) {
 // block: rows (y, z0..z0+ZB) of SPB consecutive slots.  The orbital values of
 // the next slot are loaded into registers before the current slot's
 // transform, so its loads overlap the current slot's LDS work and stores.
+// CPLX: complex orbitals (psi holds (re, im) pairs), one pair per slot, and
+// Z = conj(psi_j) psi_i (Eq. 2).
 // ---------------------------------------------------------------------------
-template <typename T, int N, int NCLS, int ZB, int NT, int SPB, bool W>
+template <typename T, int N, int NCLS, int ZB, int NT, int SPB, bool W, bool CPLX>
 __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>* __restrict__ X,
                                                const Slot* __restrict__ slots, int slot0,
                                                int nslots, const double* __restrict__ occ,
@@ -126,9 +128,28 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
     if (NCLS == 2) md[k] = mdg[k];
   }
   // orbital values of slot ls at the block's points p = tid + q NT -> (zi, x)
+  // (CPLX: va = psi_i, vb = psi_j as (re, im))
   T va[PV][2], vb[PV][2];
   auto fetch = [&](int ls) {
     const Slot sl = slots[slot0 + ls];
+    if constexpr (CPLX) {
+      const cpx<T>* pi = reinterpret_cast<const cpx<T>*>(psi) + (size_t)sl.ia * M3;
+      const cpx<T>* pj = reinterpret_cast<const cpx<T>*>(psi) + (size_t)sl.ja * M3;
+#pragma unroll
+      for (int q = 0; q < PV; ++q) {
+        const int p = tid + q * NT;
+        if ((ZB * N) % NT == 0 || p < ZB * N) {
+          const int zi = p / N, x = p % N;
+          const size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
+          const cpx<T> u = pi[o], v = pj[o];
+          va[q][0] = u.x;
+          va[q][1] = u.y;
+          vb[q][0] = v.x;
+          vb[q][1] = v.y;
+        }
+      }
+      return;
+    }
     const bool ha = sl.ia >= 0, hb = sl.ib >= 0;  // either half may be empty
     const T* pia = psi + (size_t)(ha ? sl.ia : 0) * M3;
     const T* pja = psi + (size_t)(ha ? sl.ja : 0) * M3;
@@ -163,7 +184,11 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
       const int p = tid + q * NT;
       if ((ZB * N) % NT == 0 || p < ZB * N) {
         const int zi = p / N, x = p % N;
-        zb[zi * P + x] = {va[q][0] * va[q][1] * wa, vb[q][0] * vb[q][1] * wb};
+        if constexpr (CPLX)
+          zb[zi * P + x] = {(va[q][0] * vb[q][0] + va[q][1] * vb[q][1]) * wa,
+                            (va[q][1] * vb[q][0] - va[q][0] * vb[q][1]) * wa};
+        else
+          zb[zi * P + x] = {va[q][0] * va[q][1] * wa, vb[q][0] * vb[q][1] * wb};
       }
     }
     if (ls + 1 < ls1) fetch(ls + 1);
@@ -1197,6 +1222,244 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 }
 
 // ---------------------------------------------------------------------------
+// pass C for complex orbitals: one pair per slot.  Slot (a, b) of a tile pair
+// holds (I0 + a, J0 + b); its inverse transform is the complex V_ij of
+// rho_ij = conj(psi_j) psi_i (Eq. 2).  (K psi)_i gains f_j V_ij psi_j and
+// (K psi)_j gains f_i conj(V_ij) psi_i, since V_ji = conj(V_ij) for a real, even
+// kernel; e_ij = h^3 sum Re(conj(rho_ij) V_ij) is real and symmetric.  K psi
+// is complex FP64; the energy partials keep the two-half layout of the packed
+// pass with the b half zero.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+constexpr int pass_c_tile_cplx() {
+  // accumulators (tile + 1) * L1 complex FP64 per thread, and the tile's J-side
+  // orbitals in LDS: tile * n * 16 * 2 sizeof(T) bytes beside the two row buffers
+  if (sizeof(T) == 8) return N <= 32 ? 8 : (N <= 64 ? 4 : 2);
+  return N <= 64 ? 8 : 4;
+}
+
+// FP32 at n = 16: 3 waves per SIMD; from n = 32 on the complex accumulators
+// need the registers of one wave
+template <typename T, int N>
+constexpr int pass_c_cplx_min_waves() {
+  return (sizeof(T) == 4 && N <= 16) ? 3 : 1;
+}
+
+template <typename T, int N, int NCLS, int ZB, int NT, int TM>
+__global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_cplx(
+    const cpx<T>* __restrict__ X, const cpx<T>* __restrict__ psi, const double* __restrict__ occ,
+    const Slot* __restrict__ slots, const TilePair* __restrict__ tiles, int t0, int slot_base,
+    cpx<double>* __restrict__ kpsi, double* __restrict__ e_part, int want_k, int want_e,
+    int pair_out, const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ mdg, int kparts) {
+  using S = SplitAC<N>;
+  constexpr int L1 = S::L1, L2 = S::L2;
+  constexpr int P = N + 1;
+  constexpr int NL = NCLS * ZB;
+  constexpr int MAXS = TM * TM;               // slots per tile pair
+  constexpr int NW = NT / 64;
+  constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
+  static_assert(ZB * L2 == NT, "one point-owner item per thread");
+  static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
+  __shared__ cpx<T> xs[NL * P];
+  __shared__ cpx<T> xo[NL * P];
+  __shared__ cpx<T> tw[N];
+  __shared__ cpx<T> md[N];
+  __shared__ int smap[TM][TM];
+  __shared__ double fI[TM], fJ[TM];
+  __shared__ double ered[MAXS][NW];
+  __shared__ double etot[NW];
+  __shared__ cpx<T> pJs[TM][L1 * NT];
+
+  const int tid = threadIdx.x;
+  const int y = blockIdx.x / (N / ZB);
+  const int z0 = (blockIdx.x % (N / ZB)) * ZB;
+  const TilePair tp = tiles[t0 + blockIdx.y];
+  const size_t M3 = (size_t)N * N * N;
+  const int t_own = tid % L2, zi_own = tid / L2;
+  const size_t row = ((size_t)(z0 + zi_own) * N + y) * N;  // offset of the owned row
+  const int ns = tp.s1 - tp.s0;
+
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    if (NCLS == 2) md[k] = mdg[k];
+  }
+  for (int k = tid; k < TM * TM; k += NT) smap[k / TM][k % TM] = -1;
+  for (int k = tid; k < TM; k += NT) {
+    fI[k] = k < tp.nI ? occ[tp.I0 + k] : 0.0;
+    fJ[k] = k < tp.nJ ? occ[tp.J0 + k] : 0.0;
+  }
+  __syncthreads();
+  for (int k = tid; k < ns; k += NT) {
+    const Slot sl = slots[tp.s0 + k];
+    smap[sl.ia - tp.I0][sl.ja - tp.J0] = k;
+  }
+  double accJ[TM][L1][2];
+#pragma unroll
+  for (int b = 0; b < TM; ++b)
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) accJ[b][k1][0] = accJ[b][k1][1] = 0.0;
+  double ew = 0.0;
+
+  cpx<T> pf[PF];
+  auto fetch = [&](int k) {
+    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      int p = tid + q * NT;
+      if ((NL * N) % NT == 0 || p < NL * N) pf[q] = Xs[p];
+    }
+  };
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    if (b >= tp.nJ) continue;
+    const cpx<T>* po = psi + (size_t)(tp.J0 + b) * M3 + row;
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * k1];
+  }
+  __syncthreads();
+  if (ns > 0) fetch(0);
+
+  int k = 0;  // running slot index (uniform)
+#pragma unroll 1
+  for (int a = 0; a < tp.nI; ++a) {
+    double accI[L1][2];
+    cpx<T> pI[L1];
+    {
+      const cpx<T>* po = psi + (size_t)(tp.I0 + a) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        accI[k1][0] = accI[k1][1] = 0.0;
+        pI[k1] = po[t_own + L2 * k1];
+      }
+    }
+    const double fa = fI[a];
+#pragma unroll
+    for (int b = 0; b < TM; ++b) {
+      if (smap[a][b] < 0) continue;
+#pragma unroll
+      for (int q = 0; q < PF; ++q) {
+        int p = tid + q * NT;
+        if ((NL * N) % NT == 0 || p < NL * N) {
+          int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
+          xs[(cx * ZB + zi) * P + kx] = pf[q];
+        }
+      }
+      if (k + 1 < ns) fetch(k + 1);  // spectrum rows of the next slot
+      __syncthreads();
+      // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle; xs -> xo
+      constexpr int C2 = NL * L1;
+#pragma unroll
+      for (int it = tid; it < C2; it += NT) {
+        int line = it % NL, q1 = it / NL;
+        cpx<T> w[L2];
+#pragma unroll
+        for (int q2 = 0; q2 < L2; ++q2) w[q2] = xs[line * P + q1 + L1 * q2];
+        Dft<L2, 1, T>::run(w);
+#pragma unroll
+        for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q1]);
+#pragma unroll
+        for (int t = 0; t < L2; ++t) xo[line * P + t + L2 * q1] = w[t];
+      }
+      __syncthreads();
+      // inverse step 1 (per t) of both x classes, demodulated: V_ij
+      cpx<T> V[L1];
+      {
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
+        Dft<L1, 1, T>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) V[k1] = v[k1];
+        if (NCLS == 2) {
+#pragma unroll
+          for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
+          Dft<L1, 1, T>::run(v);
+#pragma unroll
+          for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
+        }
+      }
+      const bool self = tp.diag && b == a;  // the (a, a) pair updates (K psi)_a once
+      const double fb = fJ[b];
+      double e = 0.0;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        const cpx<T> pa = pI[k1], pb = pJs[b][k1 * NT + tid];
+        const cpx<T> rho = cmulc(pa, pb);
+        const double vr = (double)V[k1].x, vi = (double)V[k1].y;
+        e += (double)rho.x * vr + (double)rho.y * vi;
+        if (want_k) {
+          const double ar = pa.x, ai = pa.y, br = pb.x, bi = pb.y;
+          accI[k1][0] += fb * (vr * br - vi * bi);  // V psi_j
+          accI[k1][1] += fb * (vr * bi + vi * br);
+          if (!self) {
+            accJ[b][k1][0] += fa * (vr * ar + vi * ai);  // conj(V) psi_i
+            accJ[b][k1][1] += fa * (vr * ai - vi * ar);
+          }
+        }
+      }
+      if (want_e && pair_out) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+        if ((tid & 63) == 0) ered[k][tid >> 6] = e;
+      }
+      if (!pair_out) ew += (self ? 1.0 : 2.0) * fa * fb * e;
+      ++k;
+    }
+    if (want_k) {
+      cpx<double>* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        cpx<double> v = ko[t_own + L2 * k1];
+        v.x += accI[k1][0];
+        v.y += accI[k1][1];
+        ko[t_own + L2 * k1] = v;
+      }
+    }
+  }
+  if (want_k) {
+    // J-side sums; a diagonal tile adds them to orbitals whose row sums are in
+    // already (same block, program order)
+#pragma unroll
+    for (int b = 0; b < TM; ++b) {
+      if (b >= tp.nJ) continue;
+      cpx<double>* ko = kpsi + (size_t)(tp.J0 + b) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        cpx<double> v = ko[t_own + L2 * k1];
+        v.x += accJ[b][k1][0];
+        v.y += accJ[b][k1][1];
+        ko[t_own + L2 * k1] = v;
+      }
+    }
+  }
+  if (!want_e) return;
+  if (pair_out) {
+    __syncthreads();
+    // one partial per (slot half, row block); the b half of a slot is empty
+    for (int q = tid; q < 2 * ns; q += NT) {
+      const int kk = q >> 1, half = q & 1;
+      double sum = 0.0;
+      if (!half) {
+#pragma unroll
+        for (int w2 = 0; w2 < NW; ++w2) sum += ered[kk][w2];
+      }
+      e_part[(size_t)(2 * (tp.s0 + kk) + half) * kparts + blockIdx.x] = sum;
+    }
+  } else {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ew += __shfl_xor(ew, off);
+    if ((tid & 63) == 0) etot[tid >> 6] = ew;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int w2 = 0; w2 < NW; ++w2) sum += etot[w2];
+      e_part[(size_t)(t0 + blockIdx.y) * kparts + blockIdx.x] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pair-energy partials: pass C writes one per (slot half, row block of 16
 // z-rows: n^2/16 of them), the energy-only pass B one per (slot, slab: at most
 // 2n); k_slot_reduce sums each slot half's partials in a fixed order, so the
@@ -1328,21 +1591,26 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
     auto* Xc = static_cast<cpx<T>*>(X);
     auto* tw = static_cast<const cpx<T>*>(tb.tw);
     auto* md = static_cast<const cpx<T>*>(tb.md);
-    if (L.ncls == 2) {
+    auto go = [&]<int NCLS, bool W, bool CPLX>() {
+      hipLaunchKernelGGL((k_pass_a<T, N, NCLS, ZB, NT, SPB, W, CPLX>), grid, dim3(NT), 0, L.stream,
+                         psi, Xc, slots, slot0, nslots, occ, tw, md);
+    };
+    auto by_w = [&]<int NCLS, bool CPLX>() {
       if (weighted)
-        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, SPB, true>), grid, dim3(NT), 0, L.stream,
-                           psi, Xc, slots, slot0, nslots, occ, tw, md);
+        go.template operator()<NCLS, true, CPLX>();
       else
-        hipLaunchKernelGGL((k_pass_a<T, N, 2, ZB, NT, SPB, false>), grid, dim3(NT), 0, L.stream,
-                           psi, Xc, slots, slot0, nslots, occ, tw, md);
-    } else {
-      if (weighted)
-        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, SPB, true>), grid, dim3(NT), 0, L.stream,
-                           psi, Xc, slots, slot0, nslots, occ, tw, md);
+        go.template operator()<NCLS, false, CPLX>();
+    };
+    auto by_cls = [&]<bool CPLX>() {
+      if (L.ncls == 2)
+        by_w.template operator()<2, CPLX>();
       else
-        hipLaunchKernelGGL((k_pass_a<T, N, 1, ZB, NT, SPB, false>), grid, dim3(NT), 0, L.stream,
-                           psi, Xc, slots, slot0, nslots, occ, tw, md);
-    }
+        by_w.template operator()<1, CPLX>();
+    };
+    if (L.cplx)
+      by_cls.template operator()<true>();
+    else
+      by_cls.template operator()<false>();
     return hipGetLastError();
   });
 }
@@ -1478,17 +1746,18 @@ bool pass_b_split(int precision, int n, int ncls, int cy, int cz) {
 // Energy partials per slot half written by the split pass B (one per slab and ky-chunk).
 int split_energy_parts_used(int n, int ncls) { return ncls * n * (n / SC); }
 
-int pass_c_max_tile(int n) {
-  switch (n) {
-    case 16: return pass_c_tile<16>();
-    case 32: return pass_c_tile<32>();
-    case 48: return pass_c_tile<48>();
-    case 64: return pass_c_tile<64>();
-    case 80: return pass_c_tile<80>();
-    case 96: return pass_c_tile<96>();
-    case 112: return pass_c_tile<112>();
-    default: return pass_c_tile<128>();
-  }
+int pass_c_max_tile(int precision, int n, bool cplx) {
+  int t = 0;
+  (void)dispatch_n(n, [&]<int N>() -> hipError_t {
+    if (!cplx)
+      t = pass_c_tile<N>();
+    else if (precision == EXX_PREC_FP64_FUSED)
+      t = pass_c_tile_cplx<double, N>();
+    else
+      t = pass_c_tile_cplx<float, N>();
+    return hipSuccess;
+  });
+  return t > 0 ? t : pass_c_tile<128>();
 }
 
 template <typename T>
@@ -1504,11 +1773,26 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
       constexpr int ZB = XZ;
       constexpr int NT = ZB * 16;
       constexpr int TM = pass_c_tile<N>();
-      if (tmax > TM) return hipErrorInvalidValue;
       dim3 grid(N * (N / ZB), ntiles);
       auto* Xc = static_cast<const cpx<T>*>(X);
       auto* tw = static_cast<const cpx<T>*>(tb.tw);
       auto* md = static_cast<const cpx<T>*>(tb.md);
+      if (L.cplx) {
+        constexpr int TMC = pass_c_tile_cplx<T, N>();
+        if (tmax > TMC) return hipErrorInvalidValue;
+        auto* pc = reinterpret_cast<const cpx<T>*>(psi);
+        auto* kc = reinterpret_cast<cpx<double>*>(kpsi);
+        if (L.ncls == 2)
+          hipLaunchKernelGGL((k_pass_c_cplx<T, N, 2, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
+                             pc, occ, slots, tiles, t0, slot_base, kc, e_slot, want_k ? 1 : 0,
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
+        else
+          hipLaunchKernelGGL((k_pass_c_cplx<T, N, 1, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
+                             pc, occ, slots, tiles, t0, slot_base, kc, e_slot, want_k ? 1 : 0,
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
+        return hipGetLastError();
+      }
+      if (tmax > TM) return hipErrorInvalidValue;
       if (L.ncls == 2)
         hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,

@@ -37,6 +37,7 @@ struct Launch {
   int cy, cz;      // y and z classes
   double h3;       // volume element
   hipStream_t stream;
+  int cplx = 0;    // complex orbitals: one pair per slot, psi and K psi interleaved (re, im)
 };
 
 }  // namespace exx
@@ -47,6 +48,7 @@ struct exx_plan {
   exx::Dims m{0, 0, 0};                 // FFT points per axis
   double h3 = 0, R = 0;
   int precision = 0;
+  bool cplx = false;  // complex orbitals (EXX_PLAN_COMPLEX)
   int n_orb_max = 0;
   int device = 0;
   exx_tuning tuning{};
@@ -99,16 +101,19 @@ hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, cons
                            hipStream_t s);
 
 bool fused_supported(int precision, int n);
-int pass_c_max_tile(int n);  // largest pair-tile edge pass C supports at grid n
+// largest pair-tile edge pass C supports at grid n (complex orbitals: its
+// complex variant, whose per-tile registers and LDS are twice as large)
+int pass_c_max_tile(int precision, int n, bool cplx);
 
 // ---- plain FP64 path, exx_plain.hip ---------------------------------------
+// cplx: psi (and kpsi) hold interleaved (re, im) FP64 values
 hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs_in_launch,
-                       int n, Dims m, void* Z, hipStream_t s);
+                       int n, Dims m, void* Z, bool cplx, hipStream_t s);
 hipError_t plain_fft_axis(void* Z, int npairs, int n, Dims m, int axis, int dir, const Tables& tb,
                           hipStream_t s);
 hipError_t plain_kernel_mul(void* Z, int npairs, Dims m, const Tables& tb, hipStream_t s);
 hipError_t plain_reduce(const void* Z, const double* psi, const double* occ, const Slot* slots,
                         int slot0, int npairs_in_launch, int n, Dims m, double h3, double* kpsi,
-                        double* e_slot, bool want_k, bool want_e, hipStream_t s);
+                        double* e_slot, bool want_k, bool want_e, bool cplx, hipStream_t s);
 
 }  // namespace exx

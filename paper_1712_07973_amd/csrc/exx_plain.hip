@@ -1,6 +1,7 @@
 // exx_plain.hip -- the plain FP64 GPU path (reference implementation on the GPU).
 //
-// One orbital pair per complex transform (imaginary part zero), the full
+// One orbital pair per complex transform (imaginary part zero for real
+// orbitals; rho_ij = conj(psi_j) psi_i of Eq. 2 for complex ones), the full
 // zero-padded grid (2n on isolated axes, n on periodic ones) stored in HBM, and one launch per stage: pair build,
 // three forward axis transforms, kernel multiply, three inverse axis
 // transforms, reduction with FP64 atomics.  It follows the pair-sum scheme of
@@ -19,6 +20,8 @@ constexpr int kPitch = kLines + 1;
 
 __device__ __forceinline__ int foldk(int k, int M) { return k <= M - k ? k : M - k; }
 
+// CPLX: psi holds interleaved (re, im) values and the pair is conj(psi_j) psi_i
+template <bool CPLX>
 __global__ void k_plain_build(const double* __restrict__ psi, const Slot* __restrict__ slots,
                               int slot0, int n, Dims m, cpx<double>* __restrict__ Z) {
   const size_t m3 = (size_t)m.x * m.y * m.z;
@@ -26,17 +29,20 @@ __global__ void k_plain_build(const double* __restrict__ psi, const Slot* __rest
   const int p = blockIdx.y;
   const Slot sl = slots[slot0 + p];
   cpx<double>* zp = Z + (size_t)p * m3;
-  const double* pi = psi + (size_t)sl.ia * n3;
-  const double* pj = psi + (size_t)sl.ja * n3;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < m3;
        idx += (size_t)gridDim.x * blockDim.x) {
     int x = (int)(idx % m.x), y = (int)((idx / m.x) % m.y), z = (int)(idx / ((size_t)m.x * m.y));
-    double r = 0.0;
+    cpx<double> r{0.0, 0.0};
     if (x < n && y < n && z < n) {
       size_t o = ((size_t)z * n + y) * n + x;
-      r = pi[o] * pj[o];
+      if constexpr (CPLX) {
+        const auto* pc = reinterpret_cast<const cpx<double>*>(psi);
+        r = cmulc(pc[(size_t)sl.ia * n3 + o], pc[(size_t)sl.ja * n3 + o]);
+      } else {
+        r.x = psi[(size_t)sl.ia * n3 + o] * psi[(size_t)sl.ja * n3 + o];
+      }
     }
-    zp[idx] = {r, 0.0};
+    zp[idx] = r;
   }
 }
 
@@ -141,6 +147,8 @@ __global__ void k_plain_kmul(cpx<double>* __restrict__ Z, Dims m, const double* 
   }
 }
 
+// CPLX: e += Re(conj(rho) V), (K psi)_i += f_j V psi_j, (K psi)_j += f_i conj(V) psi_i
+template <bool CPLX>
 __global__ __launch_bounds__(256) void k_plain_reduce(const cpx<double>* __restrict__ Z,
                                                       const double* __restrict__ psi,
                                                       const double* __restrict__ occ,
@@ -154,21 +162,37 @@ __global__ __launch_bounds__(256) void k_plain_reduce(const cpx<double>* __restr
   const int p = blockIdx.y;
   const Slot sl = slots[slot0 + p];
   const cpx<double>* zp = Z + (size_t)p * m3;
-  const double* pi = psi + (size_t)sl.ia * n3;
-  const double* pj = psi + (size_t)sl.ja * n3;
-  double* ki = kpsi + (size_t)sl.ia * n3;
-  double* kj = kpsi + (size_t)sl.ja * n3;
+  const int vals = CPLX ? 2 : 1;  // doubles per grid value
+  const double* pi = psi + (size_t)sl.ia * n3 * vals;
+  const double* pj = psi + (size_t)sl.ja * n3 * vals;
+  double* ki = kpsi + (size_t)sl.ia * n3 * vals;
+  double* kj = kpsi + (size_t)sl.ja * n3 * vals;
   const double fi = occ[sl.ia], fj = occ[sl.ja];
   double e = 0.0;
   for (size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x; o < n3;
        o += (size_t)gridDim.x * blockDim.x) {
     int x = (int)(o % n), y = (int)((o / n) % n), z = (int)(o / ((size_t)n * n));
-    double V = zp[((size_t)z * m.y + y) * m.x + x].x;
-    double a = pi[o], b = pj[o];
-    e += a * b * V;
-    if (want_k) {
-      atomicAdd(&ki[o], fj * V * b);
-      if (sl.ia != sl.ja) atomicAdd(&kj[o], fi * V * a);
+    const cpx<double> V = zp[((size_t)z * m.y + y) * m.x + x];
+    if constexpr (CPLX) {
+      const cpx<double> a{pi[2 * o], pi[2 * o + 1]}, b{pj[2 * o], pj[2 * o + 1]};
+      const cpx<double> rho = cmulc(a, b);
+      e += rho.x * V.x + rho.y * V.y;
+      if (want_k) {
+        const cpx<double> u = cmul(V, b), w = cmulc(a, V);  // V psi_j, conj(V) psi_i
+        atomicAdd(&ki[2 * o], fj * u.x);
+        atomicAdd(&ki[2 * o + 1], fj * u.y);
+        if (sl.ia != sl.ja) {
+          atomicAdd(&kj[2 * o], fi * w.x);
+          atomicAdd(&kj[2 * o + 1], fi * w.y);
+        }
+      }
+    } else {
+      double a = pi[o], b = pj[o];
+      e += a * b * V.x;
+      if (want_k) {
+        atomicAdd(&ki[o], fj * V.x * b);
+        if (sl.ia != sl.ja) atomicAdd(&kj[o], fi * V.x * a);
+      }
     }
   }
   if (!want_e) return;
@@ -206,11 +230,16 @@ unsigned grid_for(size_t count) {
 }  // namespace
 
 hipError_t plain_build(const double* psi, const Slot* slots, int slot0, int npairs, int n, Dims m,
-                       void* Z, hipStream_t s) {
+                       void* Z, bool cplx, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   size_t m3 = (size_t)m.x * m.y * m.z;
-  hipLaunchKernelGGL(k_plain_build, dim3(grid_for(m3), npairs), dim3(256), 0, s, psi, slots,
-                     slot0, n, m, static_cast<cpx<double>*>(Z));
+  auto* Zc = static_cast<cpx<double>*>(Z);
+  if (cplx)
+    hipLaunchKernelGGL(k_plain_build<true>, dim3(grid_for(m3), npairs), dim3(256), 0, s, psi,
+                       slots, slot0, n, m, Zc);
+  else
+    hipLaunchKernelGGL(k_plain_build<false>, dim3(grid_for(m3), npairs), dim3(256), 0, s, psi,
+                       slots, slot0, n, m, Zc);
   return hipGetLastError();
 }
 
@@ -243,13 +272,17 @@ hipError_t plain_kernel_mul(void* Z, int npairs, Dims m, const Tables& tb, hipSt
 
 hipError_t plain_reduce(const void* Z, const double* psi, const double* occ, const Slot* slots,
                         int slot0, int npairs, int n, Dims m, double h3, double* kpsi,
-                        double* e_slot, bool want_k, bool want_e, hipStream_t s) {
+                        double* e_slot, bool want_k, bool want_e, bool cplx, hipStream_t s) {
   (void)h3;
   if (npairs <= 0) return hipSuccess;
   size_t n3 = (size_t)n * n * n;
-  hipLaunchKernelGGL(k_plain_reduce, dim3(grid_for(n3), npairs), dim3(256), 0, s,
-                     static_cast<const cpx<double>*>(Z), psi, occ, slots, slot0, n, m, kpsi,
-                     e_slot, want_k ? 1 : 0, want_e ? 1 : 0);
+  auto* Zc = static_cast<const cpx<double>*>(Z);
+  if (cplx)
+    hipLaunchKernelGGL(k_plain_reduce<true>, dim3(grid_for(n3), npairs), dim3(256), 0, s, Zc, psi,
+                       occ, slots, slot0, n, m, kpsi, e_slot, want_k ? 1 : 0, want_e ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_plain_reduce<false>, dim3(grid_for(n3), npairs), dim3(256), 0, s, Zc, psi,
+                       occ, slots, slot0, n, m, kpsi, e_slot, want_k ? 1 : 0, want_e ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -33,12 +33,12 @@ std::vector<std::vector<std::pair<int, int>>> tile_rounds(int nt) {
   return rounds;
 }
 
-void build_schedule_host(int N, int T, int batch_slots, bool packed, Schedule& s) {
+void build_schedule_host(int N, int T, int batch_slots, int packing, Schedule& s) {
   s = Schedule();
   s.n_orb = N;
   s.n_pairs = (long long)N * (N + 1) / 2;
   s.batch_slots = batch_slots;
-  if (!packed) {
+  if (packing == kPlain) {
     s.tile = 0;
     for (int i = 0; i < N; ++i)
       for (int j = i; j < N; ++j) s.slots.push_back({i, j, -1, -1});
@@ -61,11 +61,16 @@ void build_schedule_host(int N, int T, int batch_slots, bool packed, Schedule& s
       tp.J0 = J * T;
       tp.nJ = std::min(T, N - tp.J0);
       tp.diag = (I == J);
-      // slot (a, bb) holds the pairs (I0 + a, J0 + 2bb) and (I0 + a, J0 + 2bb + 1);
-      // a half outside the tile (ragged edge) or below the diagonal is empty
-      // (orbital index -1).  Fully empty slots are not emitted.
+      // kPacked: slot (a, bb) holds the pairs (I0 + a, J0 + 2bb) and
+      // (I0 + a, J0 + 2bb + 1); a half outside the tile (ragged edge) or below the
+      // diagonal is empty (orbital index -1).  Fully empty slots are not emitted.
+      // kTiled: slot (a, b) holds the pair (I0 + a, J0 + b), b >= a on the diagonal.
       tp.s0 = (int)s.slots.size();
-      for (int a = 0; a < tp.nI; ++a)
+      if (packing == kTiled) {
+        for (int a = 0; a < tp.nI; ++a)
+          for (int b = tp.diag ? a : 0; b < tp.nJ; ++b) s.slots.push_back({tp.I0 + a, tp.J0 + b, -1, -1});
+      }
+      for (int a = 0; packing == kPacked && a < tp.nI; ++a)
         for (int bb = 0; 2 * bb < tp.nJ; ++bb) {
           Slot sl{-1, -1, -1, -1};
           for (int h = 0; h < 2; ++h) {
@@ -83,7 +88,7 @@ void build_schedule_host(int N, int T, int batch_slots, bool packed, Schedule& s
     }
   // chunks of whole tile pairs whose slots fit the launch capacity; pass C
   // segments split chunks at round boundaries
-  const int cap = std::max(batch_slots, T * ((T + 1) / 2));
+  const int cap = std::max(batch_slots, packing == kTiled ? T * T : T * ((T + 1) / 2));
   int t0 = 0;
   while (t0 < (int)s.tiles.size()) {
     int t1 = t0;

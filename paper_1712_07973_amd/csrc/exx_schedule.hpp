@@ -9,7 +9,9 @@ namespace exx {
 // One packed slot = two unordered pairs (ia, ja) and (ib, jb) sharing one
 // complex transform (real part: pair a, imaginary part: pair b); a negative
 // orbital index marks an empty half.  Within a pair tile the slot of row a and
-// column pair bb holds (I0 + a, J0 + 2bb) and (I0 + a, J0 + 2bb + 1).
+// column pair bb holds (I0 + a, J0 + 2bb) and (I0 + a, J0 + 2bb + 1).  With
+// complex orbitals a slot holds one pair (ia, ja) (the b half is empty) and the
+// slot of row a and column b holds (I0 + a, J0 + b).
 struct Slot {
   int ia, ja, ib, jb;
 };
@@ -42,12 +44,16 @@ struct Schedule {
   TilePair* d_tiles = nullptr;
 };
 
+// Slot packing of a schedule.
+enum Packing {
+  kPlain = 0,   // one pair per slot in (i <= j) order, chunks of batch_slots (the plain path)
+  kPacked = 1,  // tiles of edge `tile`, tile pairs in round-robin rounds, two real pairs
+                // per slot, chunks of whole tile pairs within batch_slots
+  kTiled = 2    // as kPacked with one pair per slot (complex orbitals)
+};
+
 // Builds the schedule for n_orb orbitals.
-//   packed = false: one pair per slot in (i <= j) order, chunks of batch_slots
-//                   (the plain path);
-//   packed = true : tiles of edge `tile`, tile pairs in round-robin rounds, two
-//                   pairs per slot, chunks of whole tile pairs within batch_slots.
-void build_schedule_host(int n_orb, int tile, int batch_slots, bool packed, Schedule& s);
+void build_schedule_host(int n_orb, int tile, int batch_slots, int packing, Schedule& s);
 
 // Rounds of a round-robin tournament over nt tiles; the first round holds the
 // diagonal pairs (I, I).  No two pairs of one round share a tile.

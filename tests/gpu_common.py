@@ -24,26 +24,27 @@ def say(msg: str) -> None:
 
 
 def small_system(bc: str, n: int, N: int, seed: int, frac: int = 0, ptype: bool = False,
-                 h: float = 0.4):
+                 h: float = 0.4, kmax: float = 0.0):
     rec = OrbitalRecipe(n=n, h=h, n_orb=N, n_gauss=3,
                         sigma=(0.8, 1.6) if bc == "periodic" else (0.6, 1.5),
                         centres={"periodic": "box", "free": "middle", "surface": "slab",
                                  "wire": "rod"}[bc],
-                        bc=bc, ptype=ptype, frac_last=frac, seed=seed)
+                        bc=bc, ptype=ptype, frac_last=frac, seed=seed, kmax=kmax)
     return make_system(rec)
 
 
 @functools.lru_cache(maxsize=None)
-def oracle_result(bc: str, n: int, N: int, seed: int, frac: int = 0, ptype: bool = False):
-    s = small_system(bc, n, N, seed, frac, ptype)
+def oracle_result(bc: str, n: int, N: int, seed: int, frac: int = 0, ptype: bool = False,
+                  kmax: float = 0.0):
+    s = small_system(bc, n, N, seed, frac, ptype, kmax=kmax)
     r = oracle.exx(s.psi, s.occ, s.h, bc, symmetric=True)
     return s, r
 
 
 def kpsi_rel_err(a: np.ndarray, b: np.ndarray) -> float:
     N = a.shape[0]
-    num = np.sqrt(((a - b).reshape(N, -1) ** 2).sum(1))
-    den = np.sqrt((b.reshape(N, -1) ** 2).sum(1))
+    num = np.sqrt((np.abs(a - b).reshape(N, -1) ** 2).sum(1))
+    den = np.sqrt((np.abs(b).reshape(N, -1) ** 2).sum(1))
     return float(np.max(num / np.maximum(den, 1e-300)))
 
 

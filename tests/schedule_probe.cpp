@@ -1,4 +1,4 @@
-// Prints the packed pair schedule for (n_orb, tile, batch_slots) as text, for
+// Prints the pair schedule for (n_orb, tile, batch_slots, packing) as text, for
 // the host-side schedule tests:  S ia ja ib jb / T s0 s1 I0 nI J0 nJ diag /
 // C t0 t1 s0 s1 seg0 seg1 / G t0 t1
 #include <cstdio>
@@ -9,9 +9,9 @@
 int main(int argc, char** argv) {
   if (argc < 5) return 2;
   int N = std::atoi(argv[1]), T = std::atoi(argv[2]), cap = std::atoi(argv[3]);
-  bool packed = std::atoi(argv[4]) != 0;
+  int packing = std::atoi(argv[4]);  // exx::Packing
   exx::Schedule s;
-  exx::build_schedule_host(N, T, cap, packed, s);
+  exx::build_schedule_host(N, T, cap, packing, s);
   std::printf("P %lld %d %d\n", s.n_pairs, s.tile, s.n_rounds);
   for (auto& x : s.slots) std::printf("S %d %d %d %d\n", x.ia, x.ja, x.ib, x.jb);
   for (auto& t : s.tiles) std::printf("T %d %d %d %d %d %d %d\n", t.s0, t.s1, t.I0, t.nI, t.J0, t.nJ, t.diag);

@@ -5,7 +5,9 @@
   slot per tile pair);
 * the tile pairs of one pass-C launch (a segment) share no orbital, which is
   what lets pass C update K psi with plain read-modify-writes;
-* chunks cover the slots contiguously and respect the slot capacity.
+* chunks cover the slots contiguously and respect the slot capacity;
+* with complex orbitals (one pair per slot) slot (a, b) of a tile pair holds
+  (I0 + a, J0 + b), with the same round and chunk structure.
 """
 import itertools
 import os
@@ -28,8 +30,13 @@ def probe(tmp_path_factory):
     return exe
 
 
-def run(probe, N, T, cap, packed=True):
-    out = subprocess.run([probe, str(N), str(T), str(cap), "1" if packed else "0"],
+PLAIN, PACKED, TILED = 0, 1, 2  # slot packings of exx_schedule.hpp
+
+
+def run(probe, N, T, cap, packed=True, packing=None):
+    if packing is None:
+        packing = PACKED if packed else PLAIN
+    out = subprocess.run([probe, str(N), str(T), str(cap), str(packing)],
                          capture_output=True, text=True, check=True).stdout.split("\n")
     rec = {"S": [], "T": [], "C": [], "G": []}
     head = None
@@ -108,3 +115,27 @@ def test_plain_schedule_is_one_pair_per_slot(probe):
     assert [s[:2] for s in r["S"]] == [(i, j) for i in range(6) for j in range(i, 6)]
     assert all(s[2] == -1 for s in r["S"])
     assert [c[2:4] for c in r["C"]] == [(0, 4), (4, 8), (8, 12), (12, 16), (16, 20), (20, 21)]
+
+
+@pytest.mark.parametrize("N,T,cap", [(1, 4, 64), (5, 4, 3), (8, 4, 1 << 20), (33, 4, 40),
+                                     (37, 8, 17), (64, 8, 100)])
+def test_single_pair_tiled_schedule_invariants(probe, N, T, cap):
+    head, r = run(probe, N, T, cap, packing=TILED)
+    assert head[0] == N * (N + 1) // 2
+    assert all(s[2] == -1 and s[3] == -1 for s in r["S"])
+    assert sorted(s[:2] for s in r["S"]) == [(i, j) for i in range(N) for j in range(i, N)]
+    for s0, s1, I0, nI, J0, nJ, diag in r["T"]:
+        expect = [(I0 + a, J0 + b) for a in range(nI) for b in range(nJ) if not diag or b >= a]
+        assert [s[:2] for s in r["S"][s0:s1]] == expect
+    for t0, t1 in r["G"]:
+        seen = set()
+        for s0, s1, I0, nI, J0, nJ, diag in r["T"][t0:t1]:
+            orbs = set(range(I0, I0 + nI)) | set(range(J0, J0 + nJ))
+            assert not (orbs & seen)
+            seen |= orbs
+    s_prev, t_prev = 0, 0
+    for t0, t1, s0, s1, g0, g1 in r["C"]:
+        assert t0 == t_prev and s0 == s_prev
+        assert s1 - s0 <= max(cap, T * T)
+        t_prev, s_prev = t1, s1
+    assert s_prev == len(r["S"]) and t_prev == len(r["T"])
