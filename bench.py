@@ -38,20 +38,22 @@ CLASSES = {"free": (2, 2, 2), "surface": (1, 1, 2), "wire": (2, 2, 1),
            "periodic": (1, 1, 1)}  # parity classes per axis x, y, z
 
 
-def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int) -> dict:
+def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int, cplx: bool = False) -> dict:
     """Minimum HBM bytes of each pass of one evaluation (FP32 path).
 
-    Per packed slot the spectrum X holds ncls * n^3 complex FP32 values:
-    pass A writes it, pass B reads and rewrites it, pass C reads it.  The
-    orbitals (FP32 copy) are read once by A and once by C; K psi (FP64) is
-    written once.  Pass B's kernel table is shared by all slots (cache
-    resident) and not counted.
+    Per slot (two real pairs, or one complex pair) the spectrum X holds
+    ncls * n^3 complex FP32 values: pass A writes it, pass B reads and
+    rewrites it, pass C reads it.  The orbitals (FP32 copy) are read once by
+    A and once by C; K psi (FP64) is written once; complex orbitals double
+    both.  Pass B's kernel table is shared by all slots (cache resident) and
+    not counted.
     """
+    v = 2 if cplx else 1  # reals per orbital value
     x = ncls * n ** 3 * 8
-    orb32 = n_orb * n ** 3 * 4
-    kps = n_orb * n ** 3 * 8
+    orb32 = n_orb * n ** 3 * 4 * v
+    kps = n_orb * n ** 3 * 8 * v
     return {
-        "convert": n_orb * n ** 3 * (8 + 4),
+        "convert": n_orb * n ** 3 * (8 + 4) * v,
         "pass_a": n_slots * x + orb32,
         "pass_b": n_slots * 2 * x,
         "pass_c": n_slots * x + orb32 + kps,
@@ -155,7 +157,9 @@ def workload_text(sysm, pairs: int) -> str:
             "periodic": f"periodic {n}^3 grid, h={h} bohr"}[sysm.bc]
     occ = "occupations 2" if float(sysm.occ.min()) == float(sysm.occ.max()) == 2.0 \
         else "occupations 2 with fractional tail"
-    return (f"{geom}, {N} Loewdin-orthonormalised Gaussian orbitals, {occ}, "
+    kind = (f"complex (phases |k| <= {sysm.recipe.kmax:g} bohr^-1) " if sysm.psi.dtype.kind == "c"
+            else "")
+    return (f"{geom}, {N} Loewdin-orthonormalised {kind}Gaussian orbitals, {occ}, "
             f"{pairs} pair solves, E_x + K psi")
 
 
@@ -318,8 +322,9 @@ def main(argv=None) -> int:
     occ = torch.from_numpy(sysm.occ).to(dev)
     kpsi = torch.empty_like(psi)
     ex = torch.empty((), dtype=torch.float64, device=dev)
+    cplx = psi.is_complex()
 
-    plan = exx.Plan(grid, "fp32", n_orb_max=N)
+    plan = exx.Plan(grid, "fp32", n_orb_max=N, complex_orbitals=cplx)
     plan.set_tuning(tile=a.tile, slab_threads=a.slab_threads, batch_slots=a.batch_slots,
                     streams=a.streams)
     plan.workspace(N)
@@ -336,7 +341,7 @@ def main(argv=None) -> int:
     dom_ms, dom_launches = passes[dom]
     per_launch_ms = dom_ms / dom_launches
     launches_per_step = dom_launches / a.steps
-    alg = algorithmic_bytes(n, ncls, N, n_slots)
+    alg = algorithmic_bytes(n, ncls, N, n_slots, cplx)
     flops = fft_flops(n, classes, n_slots, share_y=(classes[2] == 2 and n <= 64))
     bytes_per_launch = alg[dom] / launches_per_step
     achieved_gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
@@ -370,7 +375,9 @@ def main(argv=None) -> int:
         "config": {"workload": workload_text(sysm, pairs),
                    "preset": a.workload, "n": n,
                    "fft_grid": [c * n for c in classes], "n_orb": N,
-                   "pairs": pairs, "packed_slots": n_slots, "tuning": plan.tuning},
+                   "orbitals": "complex" if cplx else "real", "pairs": pairs,
+                   "slots": n_slots, "pairs_per_slot": 1 if cplx else 2,
+                   "tuning": plan.tuning},
         "roofline": roofline,
         "whole_step_algorithmic_GBs": round(whole_alg / (ms * 1e-3) / 1e9, 1),
         "passes_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in passes.items()},
@@ -380,7 +387,7 @@ def main(argv=None) -> int:
 
     if not a.no_baselines:
         for prec in ("fp64_plain", "fp64_fused"):
-            p64 = exx.Plan(grid, prec, n_orb_max=N)
+            p64 = exx.Plan(grid, prec, n_orb_max=N, complex_orbitals=cplx)
             p64.workspace(N)
             k64 = torch.empty_like(psi)
             e64 = torch.empty((), dtype=torch.float64, device=dev)

@@ -37,6 +37,12 @@ def recipe(name: str) -> OrbitalRecipe:
         # in-plane distance L), periodic along z (L = 25.6 bohr); 32 orbitals
         return OrbitalRecipe(n=64, h=H, n_orb=32, n_gauss=4, sigma=(0.6, 1.5),
                              centres="rod", bc=WIRE, seed=1007)
+    if name == "free64_n32_complex":
+        # free64_n32's grid and orbital count with complex orbitals: every Gaussian
+        # term carries a phase exp(i k.(r - A)), |k_a| <= 1 bohr^-1, and a unit
+        # complex coefficient
+        return OrbitalRecipe(n=64, h=H, n_orb=32, n_gauss=4, sigma=(0.6, 1.5),
+                             centres="middle", bc=FREE, seed=1008, kmax=1.0)
     if name == "free128_n256":
         # isolated, 128^3 grid zero-padded to 256^3, 256 orbitals, last 16 fractional
         return OrbitalRecipe(n=128, h=H, n_orb=256, n_gauss=4, sigma=(0.6, 1.5),
@@ -45,7 +51,7 @@ def recipe(name: str) -> OrbitalRecipe:
 
 
 SINGLE = ("periodic32_n8", "free64_n32", "periodic96_n128", "free128_n256", "surface64_n32",
-          "wire64_n32")
+          "wire64_n32", "free64_n32_complex")
 BATCH = "batch16_free"
 
 

@@ -194,17 +194,22 @@ typedef struct exx_system {
 
 typedef struct exx_batch exx_batch;
 
-/* A batch of n_systems independent systems of real orbitals (any mix of
- * supported grids and orbital counts, one precision; e.g. the two spin
- * channels of one system).  Each system keeps its own plan (kernels are
- * specialised per grid size); the systems are issued on a few side streams
- * forked from `stream` (largest first) so that they overlap, and joined back.
- * With use_graph != 0 the whole evaluation is captured into one HIP graph on
- * the first exx_batch_compute and replayed afterwards, one graph launch per
- * call (the system pointers, mode, flags, workspace and stream must then stay
- * the same; a change recaptures). */
+/* Flags of exx_batch_create. */
+#define EXX_BATCH_GRAPH 1u   /* capture the evaluation into a HIP graph and replay it */
+#define EXX_BATCH_COMPLEX 2u /* every system has complex orbitals (as EXX_PLAN_COMPLEX) */
+
+/* A batch of n_systems independent systems (any mix of supported grids and
+ * orbital counts, one precision, all real or all complex orbitals; e.g. the
+ * two spin channels of a spin-polarized system, Eq. 2's sum over sigma).  Each
+ * system keeps its own plan (kernels are specialised per grid size); the
+ * systems are issued on a few side streams forked from `stream` (largest
+ * first) so that they overlap, and joined back.  With EXX_BATCH_GRAPH the
+ * whole evaluation is captured into one HIP graph on the first
+ * exx_batch_compute and replayed afterwards, one graph launch per call (the
+ * system pointers, mode, flags, workspace and stream must then stay the same;
+ * a change recaptures).  Unknown flag bits give EXX_ERR_INVALID_ARG. */
 int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
-                     int precision, int use_graph);
+                     int precision, unsigned flags);
 void exx_batch_destroy(exx_batch* batch);
 int exx_batch_workspace_bytes(const exx_batch* batch, size_t* bytes);
 int exx_batch_compute(exx_batch* batch, const exx_system* systems, int mode, unsigned flags,

@@ -18,6 +18,7 @@ PREC_FP32, PREC_FP64_PLAIN, PREC_FP64_FUSED = 0, 1, 2
 MODE_ENERGY, MODE_KPSI, MODE_ENERGY_KPSI = 1, 2, 3
 FLAG_ACCUMULATE = 1
 PLAN_COMPLEX = 1
+BATCH_GRAPH, BATCH_COMPLEX = 1, 2
 
 ERRORS = {
     0: "EXX_OK", -1: "EXX_ERR_INVALID_ARG", -2: "EXX_ERR_UNSUPPORTED_SIZE", -3: "EXX_ERR_CAPACITY",
@@ -63,7 +64,7 @@ SIGNATURES = {
     "exx_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p, C.c_int, C.c_char_p]),
     "exx_batch_create": (C.c_int, [C.POINTER(C.c_void_p), C.POINTER(ExxGrid), C.POINTER(C.c_int),
-                                   C.c_int, C.c_int, C.c_int]),
+                                   C.c_int, C.c_int, C.c_uint]),
     "exx_batch_destroy": (None, [C.c_void_p]),
     "exx_batch_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "exx_batch_compute": (C.c_int, [C.c_void_p, C.POINTER(ExxSystem), C.c_int, C.c_uint, C.c_void_p,

@@ -13,22 +13,27 @@ class Batch:
     """Evaluates many systems (mixed grids and orbital counts) per call.
 
     With ``use_graph`` the first call captures the whole evaluation into a HIP
-    graph and later calls with the same tensors replay it.
+    graph and later calls with the same tensors replay it.  With
+    ``complex_orbitals`` every system's psi is complex128.  The two spin
+    channels of a spin-polarized system are a batch of two systems.
     """
 
     def __init__(self, grids: list[Grid], n_orb: list[int], precision: str = "fp32",
-                 use_graph: bool = True, device: torch.device | None = None):
+                 use_graph: bool = True, device: torch.device | None = None,
+                 complex_orbitals: bool = False):
         if len(grids) != len(n_orb) or not grids:
             raise ValueError("grids and n_orb must be non-empty lists of equal length")
         self.grids = list(grids)
         self.n_orb = [int(x) for x in n_orb]
         self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.dtype = torch.complex128 if complex_orbitals else torch.float64
+        flags = (L.BATCH_GRAPH if use_graph else 0) | (L.BATCH_COMPLEX if complex_orbitals else 0)
         arr = (L.ExxGrid * len(grids))(*[g.to_c() for g in grids])
         na = (C.c_int * len(grids))(*self.n_orb)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             L.check(L.lib().exx_batch_create(C.byref(h), arr, na, len(grids),
-                                             PRECISIONS[precision], 1 if use_graph else 0),
+                                             PRECISIONS[precision], flags),
                     "exx_batch_create")
         self._h = h
         size = C.c_size_t()
@@ -62,7 +67,7 @@ class Batch:
         sysarr = (L.ExxSystem * S)()
         for s in range(S):
             n = self.grids[s].n
-            _check_tensor("psi", psis[s], (self.n_orb[s], n, n, n), self.device)
+            _check_tensor("psi", psis[s], (self.n_orb[s], n, n, n), self.device, self.dtype)
             _check_tensor("occ", occs[s], (self.n_orb[s],), self.device)
             ex, kp = outputs[s]
             sysarr[s].psi = psis[s].data_ptr()

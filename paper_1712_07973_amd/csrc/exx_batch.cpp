@@ -64,16 +64,18 @@ bool same_systems(const std::vector<exx_system>& a, const exx_system* b, size_t 
 extern "C" {
 
 int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
-                     int precision, int use_graph) {
+                     int precision, unsigned flags) {
   if (!out || !grids || !n_orb || n_systems <= 0) return EXX_ERR_INVALID_ARG;
+  if ((flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_COMPLEX)) != 0) return EXX_ERR_INVALID_ARG;
   *out = nullptr;
   exx_batch* b = new (std::nothrow) exx_batch();
   if (!b) return EXX_ERR_INTERNAL;
-  b->use_graph = use_graph;
+  b->use_graph = (flags & EXX_BATCH_GRAPH) != 0;
+  const unsigned plan_flags = (flags & EXX_BATCH_COMPLEX) ? EXX_PLAN_COMPLEX : 0u;
   size_t off = 0;
   for (int s = 0; s < n_systems; ++s) {
     exx_plan* p = nullptr;
-    int rc = exx_plan_create(&p, &grids[s], precision, n_orb[s], 0);
+    int rc = exx_plan_create(&p, &grids[s], precision, n_orb[s], plan_flags);
     if (rc == EXX_OK) rc = exx_plan_prepare(p, n_orb[s]);
     size_t bytes = 0;
     if (rc == EXX_OK) rc = exx_workspace_bytes(p, n_orb[s], &bytes);

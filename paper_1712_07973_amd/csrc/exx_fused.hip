@@ -1233,9 +1233,12 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 template <typename T, int N>
 constexpr int pass_c_tile_cplx() {
   // accumulators (tile + 1) * L1 complex FP64 per thread, and the tile's J-side
-  // orbitals in LDS: tile * n * 16 * 2 sizeof(T) bytes beside the two row buffers
+  // orbitals in LDS: tile * n * 16 * 2 sizeof(T) bytes beside the two row buffers.
+  // FP32 at n = 64: a tile of 8 fits one block per CU (256 registers, 100 KB of
+  // LDS) and measured 1.16 ms of pass C per evaluation of 32 orbitals against
+  // 0.90 ms with a tile of 4 (two blocks per CU, 80 % more K psi updates)
   if (sizeof(T) == 8) return N <= 32 ? 8 : (N <= 64 ? 4 : 2);
-  return N <= 64 ? 8 : 4;
+  return N <= 48 ? 8 : 4;
 }
 
 // FP32 at n = 16: 3 waves per SIMD; from n = 32 on the complex accumulators

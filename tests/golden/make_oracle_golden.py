@@ -35,6 +35,7 @@ PLANS = {
     "free128_n256": (False, 12, [250], 2048),
     "surface64_n32": (True, 0, [0, 7, 31], 2048),
     "wire64_n32": (True, 0, [0, 7, 31], 2048),
+    "free64_n32_complex": (True, 0, [0, 7, 31], 2048),
 }
 
 
@@ -76,7 +77,7 @@ def run(preset: str) -> None:
     else:
         vals = oracle.kpsi_rows(sysm.psi, sysm.occ, rows, sysm.h, sysm.bc, R=sysm.R).reshape(len(rows), -1)
     out["kpsi_values"] = vals[:, pts]
-    out["kpsi_norms"] = np.sqrt((vals ** 2).sum(axis=1))
+    out["kpsi_norms"] = np.sqrt((np.abs(vals) ** 2).sum(axis=1))
     path = os.path.join(HERE, f"{preset}_oracle.npz")
     np.savez_compressed(path, **out)
     print(f"{preset}: wrote {path} in {time.time() - t0:.0f} s", flush=True)

@@ -76,6 +76,13 @@ def test_plan_validation_precision_and_counts(lib):
     assert lib.exx_plan_create(None, C.byref(g), 0, 16, 0) == -1
     g2 = _grid(n=112)
     assert lib.exx_plan_create(C.byref(h), C.byref(g2), 2, 16, 0) == -2  # FP64_FUSED n <= 96
+    # plan flags: only EXX_PLAN_COMPLEX (1) is defined; batch flags: GRAPH (1), COMPLEX (2)
+    assert lib.exx_plan_create(C.byref(h), C.byref(g), 0, 16, 2) == -1
+    assert b"flags" in lib.exx_last_error()
+    grids = (type(g) * 1)(g)
+    counts = (C.c_int * 1)(4)
+    assert lib.exx_batch_create(C.byref(h), grids, counts, 1, 0, 4) == -1
+    assert not h.value
 
 
 def test_null_plan_calls(lib):

@@ -6,7 +6,8 @@ points (stored by tests/golden/make_oracle_golden.py, which calls only the
 oracle), plus E_x and all pair energies for the 32-orbital workload.
 Properties that hold at any size are checked on the whole output:
 E_x = -1/2 h^3 sum_i f_i <psi_i, (K psi)_i>, a symmetric non-negative
-pair-energy matrix, and E_x = -1/2 sum f_i f_j e_ij.
+pair-energy matrix, and E_x = -1/2 sum f_i f_j e_ij (with Re <psi_i, (K psi)_i>
+for the complex-orbital workload).
 """
 import functools
 import os
@@ -45,12 +46,13 @@ def evaluate(s, precision):
     psi = torch.from_numpy(s.psi).to(dev)
     occ = torch.from_numpy(s.occ).to(dev)
     g = exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc != "periodic" else None)
-    plan = exx.Plan(g, precision, n_orb_max=s.n_orb)
+    plan = exx.Plan(g, precision, n_orb_max=s.n_orb, complex_orbitals=psi.is_complex())
     pe = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=dev)
     ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)
     torch.cuda.synchronize()
-    # E_x from K psi: -1/2 h^3 sum_i f_i <psi_i, (K psi)_i>
-    dots = (psi.reshape(s.n_orb, -1) * kpsi.reshape(s.n_orb, -1)).sum(dim=1)
+    # E_x from K psi: -1/2 h^3 sum_i f_i Re <psi_i, (K psi)_i>
+    dots = (psi.conj().reshape(s.n_orb, -1) * kpsi.reshape(s.n_orb, -1)).sum(dim=1)
+    dots = dots.real if dots.is_complex() else dots
     e_from_k = float(-0.5 * s.h ** 3 * (occ * dots).sum().item())
     out = {"E": float(ex.item()), "E_from_kpsi": e_from_k, "pair_e": pe.cpu().numpy(),
            "kpsi": kpsi}
@@ -98,6 +100,11 @@ def test_surface64_n32(precision):
 @pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
 def test_wire64_n32(precision):
     check("wire64_n32", precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused", "fp64_plain"])
+def test_free64_n32_complex(precision):
+    check("free64_n32_complex", precision)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64_fused"])
