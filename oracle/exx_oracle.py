@@ -45,7 +45,12 @@ design notes):
   for G_z != 0; for G_z = 0 the transform of the 2-D potential -2 ln(rho) on
   rho < R (rho in bohr), 4 pi / G_perp^2 [1 - J0(G_perp R) - G_perp R J1(G_perp R) ln R],
   and pi R^2 (1 - 2 ln R) at G = 0;
-* G = 2 pi k / (m h) with k folded to the symmetric range (k > m/2 -> k - m).
+* G = 2 pi k / (m h) with k folded to the symmetric range (k > m/2 -> k - m);
+* kernel="isf" (free boundary): the Green's function of the paper's own
+  Poisson solver, the exact Coulomb potential at the grid points of the
+  density interpolated by order-16 scaling functions (oracle/isf.py), applied
+  as a convolution on the same doubled grid (no radius: the doubled box holds
+  every displacement).
 
 Parity pins: see tests/test_oracle_*.py (closed forms for plane waves and
 Gaussians, brute-force sums on tiny grids, invariants, finite differences).
@@ -149,8 +154,16 @@ def wire_kernel(n: int, h: float, R: float | None = None) -> np.ndarray:
 
 
 def kernel_hat(n: int, h: float, bc: str, R: float | None = None,
-               omega: float = 0.0) -> np.ndarray:
+               omega: float = 0.0, kernel: str = "coulomb") -> np.ndarray:
     """Fourier-space Green's kernel on the FFT grid (real, even in G)."""
+    if kernel == "isf":
+        if bc != FREE:
+            raise ValueError("the ISF kernel is built for the free boundary")
+        from .isf import isf_kernel_circulant
+        khat = sfft.fftn(isf_kernel_circulant(n, h), workers=_WORKERS)
+        return np.ascontiguousarray(khat.real)  # even in every axis: real up to rounding
+    if kernel != "coulomb":
+        raise ValueError(kernel)
     if bc == SURFACE:
         return surface_kernel(n, h, R)
     if bc == WIRE:
@@ -192,7 +205,8 @@ def embed(rho: np.ndarray, m) -> np.ndarray:
 
 
 def solve_poisson(rho: np.ndarray, h: float, bc: str, R: float | None = None,
-                  omega: float = 0.0, khat: np.ndarray | None = None) -> np.ndarray:
+                  omega: float = 0.0, khat: np.ndarray | None = None,
+                  kernel: str = "coulomb") -> np.ndarray:
     """V with lap V = -4 pi rho (Eq. 4) by FFT convolution with the kernel.
 
     V = crop( IFFT( K^ . FFT( embed(rho) ) ) ); V is real for a real rho.
@@ -200,7 +214,7 @@ def solve_poisson(rho: np.ndarray, h: float, bc: str, R: float | None = None,
     n = rho.shape[0]
     shape = fft_shape(n, bc)
     if khat is None:
-        khat = kernel_hat(n, h, bc, R, omega)
+        khat = kernel_hat(n, h, bc, R, omega, kernel)
     F = sfft.fftn(embed(rho, shape), workers=_WORKERS)
     V = sfft.ifftn(khat * F, workers=_WORKERS)
     V = V[:n, :n, :n]
@@ -219,7 +233,8 @@ def pair_energy(rho: np.ndarray, V: np.ndarray, h: float) -> float:
 
 
 def exx(psi: np.ndarray, occ: np.ndarray, h: float, bc: str, R: float | None = None,
-        omega: float = 0.0, symmetric: bool = False, want_kpsi: bool = True):
+        omega: float = 0.0, symmetric: bool = False, want_kpsi: bool = True,
+        kernel: str = "coulomb"):
     """E_x, K psi and the pair-energy matrix e_ij = integral rho_ij V_ij.
 
     Default: a plain double loop over *ordered* pairs (i, j), one Poisson
@@ -228,7 +243,7 @@ def exx(psi: np.ndarray, occ: np.ndarray, h: float, bc: str, R: float | None = N
     for large inputs; the symmetry itself is pinned separately.
     """
     N = psi.shape[0]
-    khat = kernel_hat(psi.shape[1], h, bc, R, omega)
+    khat = kernel_hat(psi.shape[1], h, bc, R, omega, kernel)
     e = np.zeros((N, N))
     kpsi = np.zeros_like(psi) if want_kpsi else None
     for i in range(N):
@@ -260,9 +275,9 @@ def exx_grad_occ(pair_e: np.ndarray, occ: np.ndarray) -> np.ndarray:
 
 
 def pair_energies(psi: np.ndarray, pairs, h: float, bc: str, R: float | None = None,
-                  omega: float = 0.0) -> np.ndarray:
+                  omega: float = 0.0, kernel: str = "coulomb") -> np.ndarray:
     """e_ij for a list of (i, j) pairs only (sampled checks on large inputs)."""
-    khat = kernel_hat(psi.shape[1], h, bc, R, omega)
+    khat = kernel_hat(psi.shape[1], h, bc, R, omega, kernel)
     out = []
     for i, j in pairs:
         rho = co_density(psi[i], psi[j])
@@ -271,9 +286,9 @@ def pair_energies(psi: np.ndarray, pairs, h: float, bc: str, R: float | None = N
 
 
 def kpsi_rows(psi: np.ndarray, occ: np.ndarray, rows, h: float, bc: str,
-              R: float | None = None, omega: float = 0.0) -> np.ndarray:
+              R: float | None = None, omega: float = 0.0, kernel: str = "coulomb") -> np.ndarray:
     """(K psi)_i for the listed orbitals only (N solves per orbital)."""
-    khat = kernel_hat(psi.shape[1], h, bc, R, omega)
+    khat = kernel_hat(psi.shape[1], h, bc, R, omega, kernel)
     out = np.zeros((len(rows),) + psi.shape[1:], dtype=psi.dtype)
     for r, i in enumerate(rows):
         for j in range(psi.shape[0]):
@@ -287,13 +302,17 @@ def kpsi_rows(psi: np.ndarray, occ: np.ndarray, rows, h: float, bc: str,
 # ---------------------------------------------------------------------------
 
 def realspace_kernel(n: int, h: float, bc: str, R: float | None = None,
-                     omega: float = 0.0) -> np.ndarray:
+                     omega: float = 0.0, kernel: str = "coulomb") -> np.ndarray:
     """K(d) on the m^3 grid of displacements by an explicit inverse DFT sum.
 
     K(d) = (1/m^3) sum_k K^(k) exp(+2 pi i k.d / m), evaluated with dense
     exponential matrices (O(m^4)), so that only the kernel formula is shared
-    with the FFT route.
+    with the FFT route.  The ISF kernel is defined in real space: its
+    displacement table itself.
     """
+    if kernel == "isf":
+        from .isf import isf_kernel_circulant
+        return isf_kernel_circulant(n, h)
     mz, my, mx = fft_shape(n, bc)
     khat = kernel_hat(n, h, bc, R, omega)
     E = [np.exp(2j * math.pi * np.outer(np.arange(m), np.arange(m)) / m) for m in (mz, my, mx)]
@@ -302,12 +321,12 @@ def realspace_kernel(n: int, h: float, bc: str, R: float | None = None,
 
 
 def brute_force_potential(rho: np.ndarray, h: float, bc: str, R: float | None = None,
-                          omega: float = 0.0) -> np.ndarray:
+                          omega: float = 0.0, kernel: str = "coulomb") -> np.ndarray:
     """V(g) = sum_{g'} rho(g') K((g - g') mod m), an explicit O(n^3 m^3) sum
     (m per axis)."""
     n = rho.shape[0]
     mz, my, mx = fft_shape(n, bc)
-    K = realspace_kernel(n, h, bc, R, omega)
+    K = realspace_kernel(n, h, bc, R, omega, kernel)
     V = np.zeros((n, n, n), dtype=np.result_type(rho.dtype, K.dtype))
     src = np.argwhere(np.ones((n, n, n), dtype=bool))
     for (a, b, c) in src:
