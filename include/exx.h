@@ -74,8 +74,14 @@ enum exx_bc { EXX_BC_PERIODIC = 0, EXX_BC_FREE = 1, EXX_BC_SURFACE = 2, EXX_BC_W
 /* Kernel of the pair Poisson problem.  COULOMB is 1/r (Eq. 4; truncated at R
  * for free boundaries).  SCREENED is erfc(omega r)/r, the short-range kernel of
  * screened hybrids: the paper notes only kernel 2's filter changes for them
- * (Section 3.2.3); periodic boundary only. */
-enum exx_kernel { EXX_KERNEL_COULOMB = 0, EXX_KERNEL_SCREENED = 1 };
+ * (Section 3.2.3); periodic boundary only.  ISF is the Green's function of the
+ * interpolating-scaling-function Poisson solver of Section 2.1.2 (free boundary
+ * only; R unused): the density is read as its order-16 Deslauriers-Dubuc
+ * interpolant and V is that density's exact Coulomb potential at the grid
+ * points, K(d) = hx hy hz int phi(u1) phi(u2) phi(u3) / |H (d - u)| du, applied on
+ * the doubled grid (exact: no displacement wraps).  The table is built on the
+ * host in FP64 from a 1/r Gaussian expansion (about 0.5 s at n = 128). */
+enum exx_kernel { EXX_KERNEL_COULOMB = 0, EXX_KERNEL_SCREENED = 1, EXX_KERNEL_ISF = 2 };
 
 /* Arithmetic path.
  *   FP32      : FP32 FFTs, two real pairs packed per complex transform,

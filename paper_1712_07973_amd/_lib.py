@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(_PKG, "libexx.so")
 
 # enums mirrored from include/exx.h
 BC_PERIODIC, BC_FREE, BC_SURFACE, BC_WIRE = 0, 1, 2, 3
-KERNEL_COULOMB, KERNEL_SCREENED = 0, 1
+KERNEL_COULOMB, KERNEL_SCREENED, KERNEL_ISF = 0, 1, 2
 PREC_FP32, PREC_FP64_PLAIN, PREC_FP64_FUSED = 0, 1, 2
 MODE_ENERGY, MODE_KPSI, MODE_ENERGY_KPSI = 1, 2, 3
 FLAG_ACCUMULATE = 1

@@ -26,7 +26,8 @@ class Grid:
     'wire' (isolated in x and y, periodic along z).
 
     R: truncation radius of the isolated directions (None: the box length n h).
-    kernel: 'coulomb' (1/r) or 'screened' (erfc(omega r)/r, periodic only).
+    kernel: 'coulomb' (1/r), 'screened' (erfc(omega r)/r, periodic only) or 'isf'
+    (the interpolating-scaling-function Green's function, free boundary only).
     """
 
     n: int
@@ -42,7 +43,8 @@ class Grid:
         g.hx = g.hy = g.hz = float(self.h)
         g.bc = {"periodic": L.BC_PERIODIC, "free": L.BC_FREE, "surface": L.BC_SURFACE,
                 "wire": L.BC_WIRE}[self.bc]
-        g.kernel = {"coulomb": L.KERNEL_COULOMB, "screened": L.KERNEL_SCREENED}[self.kernel]
+        g.kernel = {"coulomb": L.KERNEL_COULOMB, "screened": L.KERNEL_SCREENED,
+                    "isf": L.KERNEL_ISF}[self.kernel]
         g.R = float(self.R) if self.R else 0.0
         g.omega = float(self.omega)
         return g

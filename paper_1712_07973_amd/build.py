@@ -22,7 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libexx.so")
 ARCH = os.environ.get("EXX_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["exx_fused.hip", "exx_plain.hip", "exx_api.cpp", "exx_batch.cpp", "exx_schedule.cpp"]
+SOURCES = ["exx_fused.hip", "exx_plain.hip", "exx_api.cpp", "exx_batch.cpp", "exx_schedule.cpp",
+           "exx_isf.cpp"]
 
 COMMON = [
     "-std=c++20", "-O3", "-fPIC", f"--offload-arch={ARCH}",

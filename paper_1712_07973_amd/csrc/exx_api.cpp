@@ -91,6 +91,7 @@ double kernel_value(const exx_grid& g, double R, double Gp2, double Gz) {
 // Octant table K(fx, fy, fz) / (mx my mz) for folded indices 0..m/2 per axis
 // (fz fastest).
 std::vector<double> kernel_octant(const exx_grid& g, double R, Dims m) {
+  if (g.kernel == EXX_KERNEL_ISF) return isf_octant(g.nx, g.hx, g.hy, g.hz);
   const int hx = m.x / 2 + 1, hy = m.y / 2 + 1, hz = m.z / 2 + 1;
   std::vector<double> t((size_t)hx * hy * hz);
   const double inv = 1.0 / ((double)m.x * m.y * m.z);
@@ -464,10 +465,12 @@ int validate_grid(const exx_grid* g, int precision) {
   if (g->bc != EXX_BC_PERIODIC && g->bc != EXX_BC_FREE && g->bc != EXX_BC_SURFACE &&
       g->bc != EXX_BC_WIRE)
     return fail(EXX_ERR_INVALID_ARG, "unknown boundary condition");
-  if (g->kernel != EXX_KERNEL_COULOMB && g->kernel != EXX_KERNEL_SCREENED)
+  if (g->kernel != EXX_KERNEL_COULOMB && g->kernel != EXX_KERNEL_SCREENED && g->kernel != EXX_KERNEL_ISF)
     return fail(EXX_ERR_INVALID_ARG, "unknown kernel");
   if (g->kernel == EXX_KERNEL_SCREENED && (!(g->omega > 0) || g->bc != EXX_BC_PERIODIC))
     return fail(EXX_ERR_INVALID_ARG, "screened kernel needs omega > 0 and a periodic grid");
+  if (g->kernel == EXX_KERNEL_ISF && g->bc != EXX_BC_FREE)
+    return fail(EXX_ERR_INVALID_ARG, "the ISF kernel is built for the free boundary");
   if (precision != EXX_PREC_FP32 && precision != EXX_PREC_FP64_PLAIN && precision != EXX_PREC_FP64_FUSED)
     return fail(EXX_ERR_INVALID_ARG, "unknown precision");
   if (g->nx != g->ny || g->nx != g->nz) return fail(EXX_ERR_UNSUPPORTED_SIZE, "grid must be cubic (nx == ny == nz)");

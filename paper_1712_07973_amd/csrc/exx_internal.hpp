@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/exx.h"
+#include "exx_isf.hpp"
 #include "exx_schedule.hpp"
 
 namespace exx {

@@ -76,6 +76,11 @@ def test_plan_validation_precision_and_counts(lib):
     assert lib.exx_plan_create(None, C.byref(g), 0, 16, 0) == -1
     g2 = _grid(n=112)
     assert lib.exx_plan_create(C.byref(h), C.byref(g2), 2, 16, 0) == -2  # FP64_FUSED n <= 96
+    # the ISF kernel (2) is built for the free boundary only
+    gp = _grid(bc=0)
+    gp.kernel = 2
+    assert lib.exx_plan_create(C.byref(h), C.byref(gp), 0, 16, 0) == -1
+    assert b"ISF" in lib.exx_last_error()
     # plan flags: only EXX_PLAN_COMPLEX (1) is defined; batch flags: GRAPH (1), COMPLEX (2)
     assert lib.exx_plan_create(C.byref(h), C.byref(g), 0, 16, 2) == -1
     assert b"flags" in lib.exx_last_error()
