@@ -35,6 +35,13 @@ int hip_fail(hipError_t e, const char* where) {
   return EXX_ERR_HIP;
 }
 
+}  // namespace
+
+int exx::record_error(int code, const std::string& msg) { return fail(code, msg); }
+int exx::record_hip_error(hipError_t e, const char* where) { return hip_fail(e, where); }
+
+namespace {
+
 #define EXX_HIP(call)                            \
   do {                                           \
     hipError_t e_ = (call);                      \

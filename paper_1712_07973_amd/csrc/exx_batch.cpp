@@ -45,12 +45,14 @@ constexpr int kSideStreams = 4;
 
 namespace {
 
-thread_local std::string g_msg;
+using exx::record_error;
+using exx::record_hip_error;
 
-int set_err(int code, const std::string& m) {
-  g_msg = m;
-  return code;
-}
+#define EXX_BATCH_HIP(call)                                    \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return record_hip_error(e_, #call);  \
+  } while (0)
 
 bool same_systems(const std::vector<exx_system>& a, const exx_system* b, size_t n) {
   if (a.size() != n) return false;
@@ -65,11 +67,13 @@ extern "C" {
 
 int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
                      int precision, unsigned flags) {
-  if (!out || !grids || !n_orb || n_systems <= 0) return EXX_ERR_INVALID_ARG;
-  if ((flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_COMPLEX)) != 0) return EXX_ERR_INVALID_ARG;
+  if (!out || !grids || !n_orb || n_systems <= 0)
+    return record_error(EXX_ERR_INVALID_ARG, "out, grids and n_orb are required and n_systems > 0");
+  if ((flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_COMPLEX)) != 0)
+    return record_error(EXX_ERR_INVALID_ARG, "unknown batch flags");
   *out = nullptr;
   exx_batch* b = new (std::nothrow) exx_batch();
-  if (!b) return EXX_ERR_INTERNAL;
+  if (!b) return record_error(EXX_ERR_INTERNAL, "out of host memory");
   b->use_graph = (flags & EXX_BATCH_GRAPH) != 0;
   const unsigned plan_flags = (flags & EXX_BATCH_COMPLEX) ? EXX_PLAN_COMPLEX : 0u;
   size_t off = 0;
@@ -91,18 +95,19 @@ int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, i
   }
   b->ws_total = off;
   const int ns = std::min<int>(kSideStreams, n_systems);
-  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+  if (hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming); e != hipSuccess) {
     exx_batch_destroy(b);
-    return EXX_ERR_HIP;
+    return record_hip_error(e, "hipEventCreateWithFlags");
   }
   for (int k = 0; k < ns; ++k) {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
       if (st) (void)hipStreamDestroy(st);
       exx_batch_destroy(b);
-      return EXX_ERR_HIP;
+      return record_hip_error(e, "side stream / join event creation");
     }
     b->side.push_back(st);
     b->join.push_back(ev);
@@ -123,7 +128,7 @@ void exx_batch_destroy(exx_batch* b) {
 }
 
 int exx_batch_workspace_bytes(const exx_batch* b, size_t* bytes) {
-  if (!b || !bytes) return EXX_ERR_INVALID_ARG;
+  if (!b || !bytes) return record_error(EXX_ERR_INVALID_ARG, "batch or bytes is NULL");
   *bytes = b->ws_total;
   return EXX_OK;
 }
@@ -132,9 +137,8 @@ int exx_batch_workspace_bytes(const exx_batch* b, size_t* bytes) {
 // s mod K (largest systems first), join back into st.
 static int batch_issue(exx_batch* b, const exx_system* sys, int mode, unsigned flags, char* ws,
                        hipStream_t st) {
-  if (hipEventRecord(b->fork, st) != hipSuccess) return EXX_ERR_HIP;
-  for (auto side : b->side)
-    if (hipStreamWaitEvent(side, b->fork, 0) != hipSuccess) return EXX_ERR_HIP;
+  EXX_BATCH_HIP(hipEventRecord(b->fork, st));
+  for (auto side : b->side) EXX_BATCH_HIP(hipStreamWaitEvent(side, b->fork, 0));
   std::vector<size_t> order(b->plans.size());
   for (size_t s = 0; s < order.size(); ++s) order[s] = s;
   auto work = [&](size_t s) {
@@ -152,17 +156,19 @@ static int batch_issue(exx_batch* b, const exx_system* sys, int mode, unsigned f
                      b->side[k % b->side.size()]);
   }
   for (size_t k = 0; k < b->side.size(); ++k) {
-    if (hipEventRecord(b->join[k], b->side[k]) != hipSuccess) return EXX_ERR_HIP;
-    if (hipStreamWaitEvent(st, b->join[k], 0) != hipSuccess) return EXX_ERR_HIP;
+    EXX_BATCH_HIP(hipEventRecord(b->join[k], b->side[k]));
+    EXX_BATCH_HIP(hipStreamWaitEvent(st, b->join[k], 0));
   }
   return rc;
 }
 
 int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned flags, void* ws,
                       size_t ws_bytes, void* stream) {
-  if (!b || !sys) return EXX_ERR_INVALID_ARG;
-  if (!ws || ws_bytes < b->ws_total) return EXX_ERR_WORKSPACE;
-  if (((uintptr_t)ws % 256) != 0) return EXX_ERR_ALIGNMENT;
+  if (!b || !sys) return record_error(EXX_ERR_INVALID_ARG, "batch or systems is NULL");
+  if (!ws || ws_bytes < b->ws_total)
+    return record_error(EXX_ERR_WORKSPACE, "workspace smaller than exx_batch_workspace_bytes(): need " +
+                                               std::to_string(b->ws_total));
+  if (((uintptr_t)ws % 256) != 0) return record_error(EXX_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* wsc = static_cast<char*>(ws);
   if (!b->use_graph) return batch_issue(b, sys, mode, flags, wsc, st);
@@ -177,12 +183,12 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
     hipStream_t cs = st;
     bool own = false;
     if (cs == nullptr) {  // the legacy default stream cannot be captured
-      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return EXX_ERR_HIP;
+      EXX_BATCH_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       own = true;
     }
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    if (hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal); e != hipSuccess) {
       if (own) (void)hipStreamDestroy(cs);
-      return EXX_ERR_HIP;
+      return record_hip_error(e, "hipStreamBeginCapture");
     }
     int rc = batch_issue(b, sys, mode, flags, wsc, cs);
     hipGraph_t g = nullptr;
@@ -192,22 +198,22 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
       if (g) (void)hipGraphDestroy(g);
       return rc;
     }
-    if (e != hipSuccess) return EXX_ERR_HIP;
+    if (e != hipSuccess) return record_hip_error(e, "hipStreamEndCapture");
     b->graph = g;
-    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return EXX_ERR_HIP;
+    EXX_BATCH_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
     b->captured.assign(sys, sys + n);
     b->captured_mode = mode;
     b->captured_flags = flags;
     b->captured_ws = ws;
     b->captured_stream = st;
   }
-  if (hipGraphLaunch(b->exec, st) != hipSuccess) return EXX_ERR_HIP;
+  EXX_BATCH_HIP(hipGraphLaunch(b->exec, st));
   return EXX_OK;
 }
 
 int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, double* kpsi,
                  void* ws, size_t ws_bytes, void* stream, int budget_ms, const char* cache_path) {
-  if (!p || !psi || !occ || !kpsi) return EXX_ERR_INVALID_ARG;
+  if (!p || !psi || !occ || !kpsi) return record_error(EXX_ERR_INVALID_ARG, "plan, psi, occ and kpsi are required");
   const auto t_start = std::chrono::steady_clock::now();
   const double budget = budget_ms > 0 ? (double)budget_ms : 20000.0;
   auto spent = [&]() {
@@ -216,10 +222,10 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   };
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipDeviceProp_t prop;
-  if (hipGetDeviceProperties(&prop, p->device) != hipSuccess) return EXX_ERR_HIP;
+  EXX_BATCH_HIP(hipGetDeviceProperties(&prop, p->device));
   std::ostringstream key;
-  key << prop.gcnArchName << " n=" << p->n << " bc=" << p->grid.bc << " prec=" << p->precision
-      << " N=" << n_orb;
+  key << prop.gcnArchName << " n=" << p->n << " bc=" << p->grid.bc << " kernel=" << p->grid.kernel
+      << " prec=" << p->precision << " complex=" << (p->cplx ? 1 : 0) << " N=" << n_orb;
   // cache lookup
   if (cache_path) {
     std::ifstream f(cache_path);
@@ -243,10 +249,16 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
                                       ? std::vector<int>{256, 512}
                                       : std::vector<int>{p->tuning.slab_threads};
   std::vector<int> streams = fused ? std::vector<int>{1, 3} : std::vector<int>{1};
-  hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return EXX_ERR_HIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
   double* ex_dev = nullptr;
-  if (hipMalloc((void**)&ex_dev, sizeof(double)) != hipSuccess) return EXX_ERR_HIP;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he == hipSuccess) he = hipMalloc((void**)&ex_dev, sizeof(double));
+  if (he != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return record_hip_error(he, "autotune events / scratch scalar");
+  }
   int rc = EXX_OK;
   for (int t : tiles) {
     for (int bs : batches) {

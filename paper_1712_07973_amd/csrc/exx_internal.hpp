@@ -102,6 +102,11 @@ hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, cons
                            hipStream_t s);
 
 bool fused_supported(int precision, int n);
+
+// Record msg (or the HIP error) as this thread's exx_last_error() and return
+// the code (EXX_ERR_HIP for the second).
+int record_error(int code, const std::string& msg);
+int record_hip_error(hipError_t e, const char* where);
 // largest pair-tile edge pass C supports at grid n (complex orbitals: its
 // complex variant, whose per-tile registers and LDS are twice as large)
 int pass_c_max_tile(int precision, int n, bool cplx);

@@ -88,6 +88,7 @@ def test_plan_validation_precision_and_counts(lib):
     counts = (C.c_int * 1)(4)
     assert lib.exx_batch_create(C.byref(h), grids, counts, 1, 0, 4) == -1
     assert not h.value
+    assert b"batch flags" in lib.exx_last_error()
 
 
 def test_null_plan_calls(lib):
