@@ -241,7 +241,11 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   }
   exx_tuning base = p->tuning, best = base;
   float best_ms = 1e30f;
-  std::vector<int> tiles = {4, 8};
+  // pair-tile edges up to pass C's limit for this plan (complex plans stop lower)
+  std::vector<int> tiles;
+  for (int t : {4, 8})
+    if (t <= exx::pass_c_max_tile(p->precision, p->n, p->cplx)) tiles.push_back(t);
+  if (tiles.empty()) tiles.push_back(exx::pass_c_max_tile(p->precision, p->n, p->cplx));
   std::vector<int> batches = {64, 256, 1 << 20};
   const bool fused = p->precision != EXX_PREC_FP64_PLAIN;
   // the 512-thread slab variant exists for the FP32 path at n = 64 only
