@@ -36,6 +36,8 @@ METRIC = "orbital-pair Poisson solves/s (E_x+Kψ) FP32-batched vs FP64, HBM GB/s
 
 CLASSES = {"free": (2, 2, 2), "surface": (1, 1, 2), "wire": (2, 2, 1),
            "periodic": (1, 1, 1)}  # parity classes per axis x, y, z
+# the classes as the FP32 passes see them: the wire runs with y and z exchanged
+PASS_CLASSES = dict(CLASSES, wire=(2, 1, 2))
 
 
 def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int, cplx: bool = False) -> dict:
@@ -60,18 +62,20 @@ def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int, cplx: bool = 
     }
 
 
-def fft_flops(n: int, classes: tuple, n_slots: int, share_y: bool) -> dict:
+def fft_flops(n: int, classes: tuple, n_slots: int) -> dict:
     """Nominal 5 L log2 L flops per complex n-point line transform, per pass.
 
-    classes = (cx, cy, cz) parity classes per axis.  Pass A/C: cx x-classes of
-    n^2 lines.  Pass B, per slab (cx n slabs per slot) of n^2 points: with
-    shared y-transforms cy y-line sets forward and inverse plus cy cz z-line
-    sets forward and inverse (2n cy (1 + cz) lines), otherwise 4 n cy cz lines.
+    classes = (cx, cy, cz) parity classes per axis as pass B sees them.  Pass
+    A/C: cx x-classes of n^2 lines.  Pass B, per slab (cx n slabs per slot) of
+    n^2 points: with two z classes the y-transforms are shared by both (in
+    one launch or through the split form's scratch): cy y-line sets forward and
+    inverse plus cy cz z-line sets forward and inverse, 2n cy (1 + cz) lines;
+    with one z class 4 n cy lines.
     """
     cx, cy, cz = classes
     f = 5.0 * n * math.log2(n)
     a = n_slots * cx * n * n * f
-    per_slab = 2 * n * cy * (1 + cz) if share_y else 4 * n * cy * cz
+    per_slab = 2 * n * cy * (1 + cz) if cz == 2 else 4 * n * cy * cz
     b = n_slots * cx * n * per_slab * f
     c = n_slots * cx * n * n * f
     return {"pass_a": a, "pass_b": b, "pass_c": c}
@@ -342,7 +346,7 @@ def main(argv=None) -> int:
     per_launch_ms = dom_ms / dom_launches
     launches_per_step = dom_launches / a.steps
     alg = algorithmic_bytes(n, ncls, N, n_slots, cplx)
-    flops = fft_flops(n, classes, n_slots, share_y=(classes[2] == 2 and n <= 64))
+    flops = fft_flops(n, PASS_CLASSES[sysm.bc], n_slots)
     bytes_per_launch = alg[dom] / launches_per_step
     achieved_gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
     achieved_tflops = flops[dom] / launches_per_step / (per_launch_ms * 1e-3) / 1e12

@@ -306,7 +306,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
     EXX_PROF(EXX_PASS_ZERO);
     if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
   }
-  Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st, p->cplx ? 1 : 0};
+  Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st, p->cplx ? 1 : 0, p->swap_yz ? 1 : 0};
   // pass B over ns slots from slot s0 (spectra at Xs) on the stream of Lb: one
   // launch, or the split form in groups of w.split_slots
   auto pass_b = [&](const Launch& Lb, char* Xs, int s0, int ns) -> int {
@@ -541,6 +541,12 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
     p->R = p->n * std::min(grid->hx, std::min(grid->hy, grid->hz));
   p->precision = precision;
   p->cplx = (flags & EXX_PLAN_COMPLEX) != 0;
+  if (grid->bc == EXX_BC_WIRE && precision != EXX_PREC_FP64_PLAIN) {
+    // the fused passes see the wire with y and z exchanged: classes (2, 1, 2),
+    // so pass B transforms the periodic axis once for both padded-y classes
+    p->swap_yz = true;
+    std::swap(p->cy, p->cz);
+  }
   p->n_orb_max = n_orb_max;
   default_tuning(p);
   hipError_t e = hipGetDevice(&p->device);
@@ -558,6 +564,15 @@ int exx_plan_create(exx_plan** out, const exx_grid* grid, int precision, int n_o
     }
   }
   auto kt = kernel_octant(*grid, p->R, p->m);
+  if (p->swap_yz) {  // [fx][fy][fz] -> [fx][fz][fy], the fused passes' axis order
+    const int ex = p->m.x / 2 + 1, ey = p->m.y / 2 + 1, ez = p->m.z / 2 + 1;
+    std::vector<double> t(kt.size());
+    for (int fx = 0; fx < ex; ++fx)
+      for (int fy = 0; fy < ey; ++fy)
+        for (int fz = 0; fz < ez; ++fz)
+          t[((size_t)fx * ez + fz) * ey + fy] = kt[((size_t)fx * ey + fy) * ez + fz];
+    kt.swap(t);
+  }
   int r = EXX_OK;
   if (is_plain(p)) {
     r = upload(&p->tables.tw_n, roots<double>(p->n, p->n));

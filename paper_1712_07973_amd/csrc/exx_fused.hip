@@ -97,14 +97,16 @@ __device__ __forceinline__ T sqrt_weight(const double* occ, int i, int j) {
 // the next slot are loaded into registers before the current slot's
 // transform, so its loads overlap the current slot's LDS work and stores.
 // CPLX: complex orbitals (psi holds (re, im) pairs), one pair per slot, and
-// Z = conj(psi_j) psi_i (Eq. 2).
+// Z = conj(psi_j) psi_i (Eq. 2).  swap_yz: the spectrum's (y, z) indices are
+// the grid's (z, y), so that pass B transforms the grid's z axis first (wire
+// geometry: the periodic axis then serves both y classes).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int NCLS, int ZB, int NT, int SPB, bool W, bool CPLX>
 __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>* __restrict__ X,
                                                const Slot* __restrict__ slots, int slot0,
                                                int nslots, const double* __restrict__ occ,
                                                const cpx<T>* __restrict__ twg,
-                                               const cpx<T>* __restrict__ mdg) {
+                                               const cpx<T>* __restrict__ mdg, int swap_yz) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
@@ -140,7 +142,8 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
         const int p = tid + q * NT;
         if ((ZB * N) % NT == 0 || p < ZB * N) {
           const int zi = p / N, x = p % N;
-          const size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
+          const size_t o = swap_yz ? ((size_t)y * N + z0 + zi) * N + x
+                                   : ((size_t)(z0 + zi) * N + y) * N + x;
           const cpx<T> u = pi[o], v = pj[o];
           va[q][0] = u.x;
           va[q][1] = u.y;
@@ -160,7 +163,8 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
       const int p = tid + q * NT;
       if ((ZB * N) % NT == 0 || p < ZB * N) {
         const int zi = p / N, x = p % N;
-        const size_t o = ((size_t)(z0 + zi) * N + y) * N + x;
+        const size_t o = swap_yz ? ((size_t)y * N + z0 + zi) * N + x
+                                 : ((size_t)(z0 + zi) * N + y) * N + x;
         va[q][0] = ha ? pia[o] : T(0);
         va[q][1] = ha ? pja[o] : T(0);
         vb[q][0] = hb ? pib[o] : T(0);
@@ -998,7 +1002,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
                                                double* __restrict__ e_part, int want_k,
                                                int want_e, int pair_out,
                                                const cpx<T>* __restrict__ twg,
-                                               const cpx<T>* __restrict__ mdg, int kparts) {
+                                               const cpx<T>* __restrict__ mdg, int kparts,
+                                               int swap_yz) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
@@ -1028,7 +1033,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   const TilePair tp = tiles[t0 + blockIdx.y];
   const size_t M3 = (size_t)N * N * N;
   const int t_own = tid % L2, zi_own = tid / L2;
-  const size_t row = ((size_t)(z0 + zi_own) * N + y) * N;  // offset of the owned row
+  // offset of the owned row (swap_yz: spectrum (y, z) = grid (z, y))
+  const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
   const int ns = tp.s1 - tp.s0;
 
   for (int k = tid; k < N; k += NT) {
@@ -1253,7 +1259,8 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
     const cpx<T>* __restrict__ X, const cpx<T>* __restrict__ psi, const double* __restrict__ occ,
     const Slot* __restrict__ slots, const TilePair* __restrict__ tiles, int t0, int slot_base,
     cpx<double>* __restrict__ kpsi, double* __restrict__ e_part, int want_k, int want_e,
-    int pair_out, const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ mdg, int kparts) {
+    int pair_out, const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ mdg, int kparts,
+    int swap_yz) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
@@ -1279,7 +1286,8 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
   const TilePair tp = tiles[t0 + blockIdx.y];
   const size_t M3 = (size_t)N * N * N;
   const int t_own = tid % L2, zi_own = tid / L2;
-  const size_t row = ((size_t)(z0 + zi_own) * N + y) * N;  // offset of the owned row
+  // offset of the owned row (swap_yz: spectrum (y, z) = grid (z, y))
+  const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
   const int ns = tp.s1 - tp.s0;
 
   for (int k = tid; k < N; k += NT) {
@@ -1596,7 +1604,7 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
     auto* md = static_cast<const cpx<T>*>(tb.md);
     auto go = [&]<int NCLS, bool W, bool CPLX>() {
       hipLaunchKernelGGL((k_pass_a<T, N, NCLS, ZB, NT, SPB, W, CPLX>), grid, dim3(NT), 0, L.stream,
-                         psi, Xc, slots, slot0, nslots, occ, tw, md);
+                         psi, Xc, slots, slot0, nslots, occ, tw, md, L.swap_yz);
     };
     auto by_w = [&]<int NCLS, bool CPLX>() {
       if (weighted)
@@ -1646,7 +1654,10 @@ hipError_t launch_pass_b_cls(const Launch& L, cpx<T>* Xc, int nslots, bool energ
 }
 
 // parity classes (x, y, z) of the boundary conditions: free (2, 2, 2),
-// surface (1, 1, 2), wire (2, 2, 1), periodic (1, 1, 1)
+// surface (1, 1, 2), periodic (1, 1, 1); the wire's (2, 2, 1) runs as (2, 1, 2)
+// with the spectrum's y and z exchanged (passes A and C swap_yz, kernel table
+// [fx][fz][fy]), so that its periodic axis is transformed once for both
+// y classes (6 instead of 8 line sets per slab)
 template <typename T, int N, int CX, int CY, int CZ>
 hipError_t launch_pass_b_for(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
                              double* e_slot, int slot0, const Tables& tb, int slab_threads) {
@@ -1680,8 +1691,8 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
       if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
         return launch_pass_b_for<T, N, 1, 1, 1>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
                                                 slab_threads);
-      if (L.ncls == 2 && L.cy == 2 && L.cz == 1)
-        return launch_pass_b_for<T, N, 2, 2, 1>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
+      if (L.ncls == 2 && L.cy == 1 && L.cz == 2)  // wire, y and z exchanged
+        return launch_pass_b_for<T, N, 2, 1, 2>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
                                                 slab_threads);
       return hipErrorInvalidValue;
     }
@@ -1727,6 +1738,8 @@ hipError_t launch_pass_b_split(const Launch& L, void* X, void* Y, int nslots, bo
       return launch_split_for<T, N, 1, 1, 2>(L, Xc, Yc, nslots, energy_only, e_part, slot0, tb);
     if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
       return launch_split_for<T, N, 1, 1, 1>(L, Xc, Yc, nslots, energy_only, e_part, slot0, tb);
+    if (L.ncls == 2 && L.cy == 1 && L.cz == 2)  // wire, y and z exchanged
+      return launch_split_for<T, N, 2, 1, 2>(L, Xc, Yc, nslots, energy_only, e_part, slot0, tb);
     return hipErrorInvalidValue;
   });
 }
@@ -1788,22 +1801,22 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
         if (L.ncls == 2)
           hipLaunchKernelGGL((k_pass_c_cplx<T, N, 2, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
                              pc, occ, slots, tiles, t0, slot_base, kc, e_slot, want_k ? 1 : 0,
-                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         else
           hipLaunchKernelGGL((k_pass_c_cplx<T, N, 1, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
                              pc, occ, slots, tiles, t0, slot_base, kc, e_slot, want_k ? 1 : 0,
-                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         return hipGetLastError();
       }
       if (tmax > TM) return hipErrorInvalidValue;
       if (L.ncls == 2)
         hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
+                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
       else
         hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
-                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N));
+                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
       return hipGetLastError();
     }
   });

@@ -39,13 +39,15 @@ struct Launch {
   double h3;       // volume element
   hipStream_t stream;
   int cplx = 0;    // complex orbitals: one pair per slot, psi and K psi interleaved (re, im)
+  int swap_yz = 0; // spectrum (y, z) = grid (z, y): cy, cz above are then the grid's z and y classes
 };
 
 }  // namespace exx
 
 struct exx_plan {
   exx_grid grid;
-  int n = 0, ncls = 1, cy = 1, cz = 1;  // grid, parity classes per axis
+  int n = 0, ncls = 1, cy = 1, cz = 1;  // grid, parity classes per spectrum axis
+  bool swap_yz = false;                 // fused wire plans: spectrum y, z = grid z, y
   exx::Dims m{0, 0, 0};                 // FFT points per axis
   double h3 = 0, R = 0;
   int precision = 0;
