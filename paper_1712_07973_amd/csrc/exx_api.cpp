@@ -302,10 +302,9 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   const int kparts = energy_parts(p->n);
   char* X = ws + w.X;
   const size_t sb = slot_bytes(p);
-  {
-    EXX_PROF(EXX_PASS_ZERO);
-    if (want_k && !(flags & EXX_FLAG_ACCUMULATE)) EXX_HIP(launch_zero(kpsi, (size_t)N * n3, st));
-  }
+  // K psi needs no clearing: pass C's diagonal tile pairs (the first round,
+  // every orbital once) store their row sums unless the caller accumulates
+  const int k_mode = !want_k ? 0 : ((flags & EXX_FLAG_ACCUMULATE) ? 1 : 2);
   Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st, p->cplx ? 1 : 0, p->swap_yz ? 1 : 0};
   // pass B over ns slots from slot s0 (spectra at Xs) on the stream of Lb: one
   // launch, or the split form in groups of w.split_slots
@@ -341,7 +340,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
           const auto& sg = s.segments[g];
           EXX_PROF(EXX_PASS_C);
           EXX_HIP(launch_pass_c<T>(L, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0, c.s0,
-                                   kpsi, e_part, want_k, want_e, pair_e != nullptr, s.tile,
+                                   kpsi, e_part, k_mode, want_e, pair_e != nullptr, s.tile,
                                    p->tables));
         }
       }
@@ -389,7 +388,7 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
           const auto& sg = s.segments[g];
           EXX_PROF_ON(EXX_PASS_C, sc);
           EXX_HIP(launch_pass_c<T>(Lc, X, psiT, occ, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0,
-                                   c.s0, kpsi, e_part, want_k, want_e, pair_e != nullptr, s.tile,
+                                   c.s0, kpsi, e_part, k_mode, want_e, pair_e != nullptr, s.tile,
                                    p->tables));
         }
         last_c = p->sync_ev[ev++];

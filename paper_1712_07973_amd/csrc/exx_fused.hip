@@ -979,6 +979,9 @@ __global__ __launch_bounds__(NT) void k_pass_b3(cpx<T>* __restrict__ X, const cp
 // Energies: with pair_out, one partial per (slot half, block) for the
 // pair-energy matrix; otherwise one weighted partial per block
 // (sum over the block's pairs of w f_i f_j e_ij, w = 2 off the diagonal).
+// want_k: 0 no K psi; 1 add into K psi; 2 as 1, except that the diagonal tile
+// pairs (the first round, which holds every orbital once) store their row
+// sums, so K psi needs no clearing beforehand.
 // ---------------------------------------------------------------------------
 template <int N>
 constexpr int pass_c_tile() {  // K psi register budget: (tile + 1) * L1 FP64 values per thread
@@ -1185,8 +1188,13 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     }
     if (want_k) {
       double* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+      if (want_k == 2 && tp.diag) {  // first write of this orbital row in the evaluation
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += accI[k1];
+        for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] = accI[k1];
+      } else {
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += accI[k1];
+      }
     }
   }
   if (want_k) {
@@ -1418,9 +1426,10 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
     }
     if (want_k) {
       cpx<double>* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+      const bool first = want_k == 2 && tp.diag;  // first write of this orbital row
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
-        cpx<double> v = ko[t_own + L2 * k1];
+        cpx<double> v = first ? cpx<double>{0.0, 0.0} : ko[t_own + L2 * k1];
         v.x += accI[k1][0];
         v.y += accI[k1][1];
         ko[t_own + L2 * k1] = v;
@@ -1779,7 +1788,7 @@ int pass_c_max_tile(int precision, int n, bool cplx) {
 template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
-                         int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
+                         int slot_base, double* kpsi, double* e_slot, int k_mode, bool want_e,
                          bool pair_out, int tmax, const Tables& tb) {
   if (ntiles <= 0) return hipSuccess;
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
@@ -1800,22 +1809,22 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
         auto* kc = reinterpret_cast<cpx<double>*>(kpsi);
         if (L.ncls == 2)
           hipLaunchKernelGGL((k_pass_c_cplx<T, N, 2, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
-                             pc, occ, slots, tiles, t0, slot_base, kc, e_slot, want_k ? 1 : 0,
+                             pc, occ, slots, tiles, t0, slot_base, kc, e_slot, k_mode,
                              want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         else
           hipLaunchKernelGGL((k_pass_c_cplx<T, N, 1, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
-                             pc, occ, slots, tiles, t0, slot_base, kc, e_slot, want_k ? 1 : 0,
+                             pc, occ, slots, tiles, t0, slot_base, kc, e_slot, k_mode,
                              want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         return hipGetLastError();
       }
       if (tmax > TM) return hipErrorInvalidValue;
       if (L.ncls == 2)
         hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
-                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
+                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
                            want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
       else
         hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
-                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, want_k ? 1 : 0,
+                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
                            want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
       return hipGetLastError();
     }
@@ -1834,10 +1843,10 @@ template hipError_t launch_pass_b_split<float>(const Launch&, void*, void*, int,
                                                const Tables&);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
                                          const Slot*, const TilePair*, int, int, int, double*,
-                                         double*, bool, bool, bool, int, const Tables&);
+                                         double*, int, bool, bool, int, const Tables&);
 template hipError_t launch_pass_c<double>(const Launch&, const void*, const double*,
                                           const double*, const Slot*, const TilePair*, int, int,
-                                          int, double*, double*, bool, bool, bool, int,
+                                          int, double*, double*, int, bool, bool, int,
                                           const Tables&);
 
 }  // namespace exx

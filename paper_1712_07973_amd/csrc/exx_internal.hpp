@@ -87,8 +87,8 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
 template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
-                         int slot_base, double* kpsi, double* e_slot, bool want_k, bool want_e,
-                         bool pair_out, int tmax, const Tables& tb);
+                         int slot_base, double* kpsi, double* e_slot, int k_mode, bool want_e,
+                         bool pair_out, int tmax, const Tables& tb);  // k_mode: 0 none, 1 add, 2 diagonal tiles store
 // pass B in three launches through a scratch of ncls cy n^3 values per slot
 // (large slabs, FP32); used when pass_b_split() says so
 template <typename T>

@@ -140,3 +140,24 @@ def test_fp32_split_pass_b_within_tolerance(case):
     ex, _, _ = plan.compute(torch.from_numpy(s.psi).to(dev), torch.from_numpy(s.occ).to(dev), "energy")
     torch.cuda.synchronize()
     assert abs(ex.item() - ref["E"]) / N < TOL_FP32_E_PER_ORB
+
+
+@pytest.mark.parametrize("bc,precision,kmax", [("free", "fp32", 0.0), ("periodic", "fp64_fused", 0.0),
+                                                ("wire", "fp32", 0.0), ("free", "fp32", 1.0)])
+def test_kpsi_output_is_overwritten(bc, precision, kmax):
+    # K psi is not cleared beforehand: the first round of pass C stores every
+    # orbital row, so stale contents (NaN here) must not survive
+    say(f"[overwrite] {precision} {bc} kmax={kmax}")
+    s, ref = oracle_result(bc, 32, 10, 47, 0, kmax=kmax)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    plan = exx.Plan(grid_of(s), precision, n_orb_max=s.n_orb, complex_orbitals=kmax > 0)
+    kpsi = torch.full_like(psi, float("nan"))
+    for _ in range(2):  # and again over the previous result
+        plan.compute(psi, occ, "kpsi", kpsi=kpsi)
+        torch.cuda.synchronize()
+        K = kpsi.cpu().numpy()
+        assert np.all(np.isfinite(K))
+        tol = TOL_FP32_K if precision == "fp32" else TOL_FP64_K
+        assert kpsi_rel_err(K, ref["kpsi"]) < tol
