@@ -1188,6 +1188,15 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     }
     if (want_k) {
       double* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+      if (tp.diag) {
+        // on a diagonal tile orbital a's column sums (from rows a' < a) are
+        // complete here: one write carries both
+#pragma unroll
+        for (int b = 0; b < TM; ++b)
+          if (b == a)
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1) accI[k1] += accJ[b][k1];
+      }
       if (want_k == 2 && tp.diag) {  // first write of this orbital row in the evaluation
 #pragma unroll
         for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] = accI[k1];
@@ -1197,9 +1206,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       }
     }
   }
-  if (want_k) {
-    // J-side sums; a diagonal tile adds them to orbitals whose row sums are in
-    // already (same block, program order)
+  if (want_k && !tp.diag) {
+    // J-side sums of an off-diagonal tile
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
       if (b >= tp.nJ) continue;
@@ -1426,6 +1434,18 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
     }
     if (want_k) {
       cpx<double>* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+      if (tp.diag) {
+        // on a diagonal tile orbital a's column sums (from rows a' < a) are
+        // complete here: one write carries both
+#pragma unroll
+        for (int b = 0; b < TM; ++b)
+          if (b == a)
+#pragma unroll
+            for (int k1 = 0; k1 < L1; ++k1) {
+              accI[k1][0] += accJ[b][k1][0];
+              accI[k1][1] += accJ[b][k1][1];
+            }
+      }
       const bool first = want_k == 2 && tp.diag;  // first write of this orbital row
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
@@ -1436,9 +1456,8 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
       }
     }
   }
-  if (want_k) {
-    // J-side sums; a diagonal tile adds them to orbitals whose row sums are in
-    // already (same block, program order)
+  if (want_k && !tp.diag) {
+    // J-side sums of an off-diagonal tile
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
       if (b >= tp.nJ) continue;
