@@ -541,11 +541,14 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
     static_assert(!SHARE_Y || CZ == 2, "shared y-transforms serve two z classes");
     // the slab again for the odd y class, loaded (an L2 hit) while the even
     // class finishes, into registers its y-columns no longer need
-    cpx<T> odd[I1][L1];
+    // (up to n = 80; at n = 96 those registers would spill, and the odd class
+    // reads its slab again)
+    constexpr bool PRE_ODD = N <= 80;
+    cpx<T> odd[PRE_ODD ? I1 : 1][L1];
 #pragma unroll
     for (int cy = 0; cy < CY; ++cy) {
-      if (cy == 0)
-        F::template y_fwd1<CX>(g, U, tw, md, 0, 0, tid);
+      if (cy == 0 || !PRE_ODD)
+        F::template y_fwd1<CX>(g, U, tw, md, cy, 0, tid);
       else
         F::y_fwd1_odd_vals(odd, U, tw, md, tid);
       __syncthreads();
@@ -598,7 +601,9 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
         }
       }
       if (EONLY) {
-        if (cy == 0 && CY == 2) F::template load_slab<CX>(g, odd, tid);
+        if constexpr (PRE_ODD) {
+          if (cy == 0 && CY == 2) F::template load_slab<CX>(g, odd, tid);
+        }
         __syncthreads();
         continue;
       }
@@ -612,7 +617,9 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
           for (int k1 = 0; k1 < L1; ++k1) U[(t + L2 * k1) * PB + ky] = wacc[ii][k1];
         }
       }
-      if (cy == 0 && CY == 2) F::template load_slab<CX>(g, odd, tid);
+      if constexpr (PRE_ODD) {
+        if (cy == 0 && CY == 2) F::template load_slab<CX>(g, odd, tid);
+      }
       __syncthreads();
       F::template y_inv2<false>(U, Vb, tw, tid);
       __syncthreads();
@@ -693,7 +700,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
 
 // ---------------------------------------------------------------------------
 // pass B split in three launches for slabs whose two LDS buffers do not fit
-// (free n >= 96, surface n >= 112).  The 2-D transform of a
+// (n >= 112 with a zero-padded z axis).  The 2-D transform of a
 // slab factorises into independent 1-D transforms along y (per z column) and
 // along z (per ky line), so each launch works on chunks of SC columns or
 // lines with small LDS tiles and many blocks per CU; the y-transformed
@@ -1627,10 +1634,12 @@ template <typename T, int N, bool SY>
 constexpr int pass_b_threads() {
   // a few items per thread; where LDS allows one block per CU (the shared-y
   // variant from N = 80 on, the single-buffer one from N = 96 on) the block
-  // takes the whole CU (16 waves) to keep per-thread arrays small
+  // takes the whole CU (16 waves) to keep per-thread arrays small; the shared-y
+  // block at N = 96 has 768 threads (one item each, 168 registers)
   if (N <= 32) return 128;
   if (N <= 64) return 256;
   if (sizeof(T) == 8) return 512;
+  if (SY && N == 96) return 768;
   return (SY || N > 80) ? 1024 : 512;
 }
 
@@ -1674,11 +1683,12 @@ template <typename T, int N, int CY, int CZ>
 constexpr bool pass_b_share_y() {
   // sharing the y-transforms needs two z classes, two slab buffers in LDS
   // (2 N (N+1) complex values) and keeps two more slab-sized register arrays
-  // live; used where that fits without spilling (measured at n = 80: pass B
-  // 6.98 -> 4.09 ms free, 2.44 -> 1.16 ms surface; n = 96 surface 4.34 -> 1.79)
+  // live; used where two buffers fit (measured at n = 80: pass B 6.98 -> 4.09 ms
+  // free, 2.44 -> 1.16 ms surface; n = 96 surface 4.34 -> 1.79, free 9.09 -> 6.67
+  // against the split form)
   if (CZ != 2) return false;
   if (sizeof(T) == 8) return N <= 32;
-  return N <= 80 || (N <= 96 && CY == 1);
+  return N <= 96;
 }
 
 template <typename T, int N, int CX, int CY, int CZ, int NT, bool SY>
@@ -1789,7 +1799,7 @@ hipError_t launch_pass_b_split(const Launch& L, void* X, void* Y, int nslots, bo
 }
 
 // Large FP32 slabs with a zero-padded z axis and without the shared-y variant
-// take the split pass B (free n >= 96, surface n >= 112).  Periodic slabs have
+// take the split pass B (n >= 112: two slab buffers no longer fit in LDS).  Periodic slabs have
 // a quarter of the classes and stay faster in one launch (n = 96: pass B 1.35
 // vs 2.22 ms split; n = 128: 2.82 vs 5.46 ms at 32 orbitals).
 bool pass_b_split(int precision, int n, int ncls, int cy, int cz) {

@@ -120,7 +120,8 @@ def test_workspace_too_small_is_rejected():
 
 
 # Large slabs on the FP32 path take the three-launch pass B (y columns, z lines,
-# inverse y columns); the FP64 fused path stops at n = 96.
+# inverse y columns) from n = 112 on; n = 96 runs the 768-thread shared-y block;
+# the FP64 fused path stops at n = 96.
 SPLIT_CASES = [("free", 96, 3, 34, 0), ("free", 112, 2, 35, 0), ("surface", 112, 3, 36, 0),
                ("free", 128, 2, 38, 0)]
 
