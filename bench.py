@@ -12,7 +12,9 @@ Prints one JSON line: pair-solves/s of the FP32 path (value), the plain FP64
 GPU path and the FP64 fused ablation beside it, per-pass device times from
 hipEvents recorded on the compute stream, the roofline of the dominant
 kernel, the accuracy against the plain FP64 path, and the FP64 CPU oracle's
-rate on a bounded sample.
+rate on a bounded sample.  The timed steps are eager calls; --graph times
+replays of one evaluation captured in a HIP graph instead (the eager rate is
+then reported beside it).
 """
 from __future__ import annotations
 
@@ -117,13 +119,10 @@ def measured_traffic(kernel: str, workload: str):
     return t.get("hbm_bytes_per_launch")
 
 
-def timed(plan, psi, occ, kpsi, ex, steps, warmup):
-    """Times `steps` evaluations after `warmup` untimed ones (no per-launch
-    events inside the timed region), then runs `steps` more with the plan's
-    per-pass hipEvents on for the pass breakdown."""
+def _time_loop(run, steps):
+    """ms per step over `steps` calls of run() (hipEvents on the current stream),
+    the median step and the host wall time."""
     import torch
-    for _ in range(warmup):
-        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -134,24 +133,53 @@ def timed(plan, psi, occ, kpsi, ex, steps, warmup):
     t_host = time.perf_counter()
     e0.record(stream)
     for k in range(steps):
-        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+        run()
         if k < steps - 1:
             marks[k].record(stream)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_host
-    ms = e0.elapsed_time(e1) / steps
     edges = [e0] + marks + [e1]
     per_step = sorted(edges[k].elapsed_time(edges[k + 1]) for k in range(steps))
-    # pass breakdown: the same evaluations with an event pair around every launch
+    median = (per_step[(steps - 1) // 2] + per_step[steps // 2]) / 2
+    return e0.elapsed_time(e1) / steps, median, wall
+
+
+def timed(plan, psi, occ, kpsi, ex, steps, warmup, use_graph=False):
+    """Times `steps` evaluations after `warmup` untimed ones, with no per-launch
+    events inside the timed region.  use_graph: the evaluation is captured once
+    into a HIP graph (torch.cuda.graph on the plan's stream) and the timed steps
+    are replays of it, as an iteration loop over fixed buffers would run it; the
+    eager rate is timed too.  Then `steps` more eager evaluations with the plan's
+    per-pass hipEvents give the pass breakdown."""
+    import torch
+
+    def eager():
+        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+
+    for _ in range(warmup):
+        eager()
+    torch.cuda.synchronize()
+    eager_ms, eager_median, eager_wall = _time_loop(eager, steps)
+    ms, median, wall = eager_ms, eager_median, eager_wall
+    if use_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            eager()
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        ms, median, wall = _time_loop(graph.replay, steps)
+    # pass breakdown: eager evaluations with an event pair around every launch
     plan.enable_profiling(True)
     plan.read_profile()
     for _ in range(steps):
-        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+        eager()
     torch.cuda.synchronize()
     prof = plan.read_profile()
     plan.enable_profiling(False)
-    prof["_median_ms"] = (per_step[(steps - 1) // 2] + per_step[steps // 2]) / 2
+    prof["_median_ms"] = median
+    prof["_eager_ms"] = eager_ms
     return ms, wall, prof
 
 
@@ -292,6 +320,9 @@ def main(argv=None) -> int:
                     help="slots per launch chunk (0: plan default)")
     ap.add_argument("--streams", type=int, default=0,
                     help="1: serial passes, 3: overlapped rounds (0: plan default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of one evaluation captured in a HIP graph (measured within "
+                         "0.5 %% of eager calls at the default workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates memory counters)")
     a = ap.parse_args(argv)
@@ -339,12 +370,13 @@ def main(argv=None) -> int:
                     streams=a.streams)
     plan.workspace(N)
     _, n_slots = plan.schedule_info(N)
-    ms, wall, prof = timed(plan, psi, occ, kpsi, ex, a.steps, a.warmup)
+    ms, wall, prof = timed(plan, psi, occ, kpsi, ex, a.steps, a.warmup, use_graph=a.graph)
     value = pairs / (ms * 1e-3)
     E32 = float(ex.item())
     K32 = kpsi.clone()
 
     median_ms = prof.pop("_median_ms")
+    eager_ms = prof.pop("_eager_ms")
     # dominant kernel and its roofline
     passes = {k: v for k, v in prof.items() if v[1] > 0}
     dom = max(("pass_a", "pass_b", "pass_c"), key=lambda k: passes.get(k, (0, 0))[0])
@@ -379,6 +411,9 @@ def main(argv=None) -> int:
         "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(ms, 4),
         "ms_per_step_median": round(median_ms, 4),
+        "timing": "replays of one evaluation captured in a HIP graph (same kernels and launches)"
+                  if a.graph else "eager evaluations",
+        "eager_ms_per_step": round(eager_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
@@ -401,7 +436,7 @@ def main(argv=None) -> int:
             p64.workspace(N)
             k64 = torch.empty_like(psi)
             e64 = torch.empty((), dtype=torch.float64, device=dev)
-            ms64, _, _ = timed(p64, psi, occ, k64, e64, a.baseline_steps, 1)
+            ms64, _, _ = timed(p64, psi, occ, k64, e64, a.baseline_steps, 1, use_graph=a.graph)
             out[prec] = {"value": round(pairs / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 3)}
             if prec == "fp64_plain":
                 E64 = float(e64.item())

@@ -71,3 +71,34 @@ def test_repeated_evaluations_are_bitwise_identical(precision):
     for r in res[1:]:
         assert r[0] == res[0][0] and r[3] == res[0][3]
         assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
+
+
+@pytest.mark.parametrize("complex_orbitals", [False, True])
+def test_single_plan_captured_in_a_torch_graph(complex_orbitals):
+    # one evaluation captured with torch.cuda.graph on the caller's stream and
+    # replayed: every replay equals the eager result bit for bit, with eager work,
+    # synchronisations and clobbered outputs between replays
+    say(f"[graph] single plan complex={complex_orbitals}")
+    s = small_system("free", 32, 9, seed=46, kmax=1.0 if complex_orbitals else 0.0)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    plan = exx.Plan(grid_of(s), "fp32", n_orb_max=s.n_orb, complex_orbitals=complex_orbitals)
+    kpsi = torch.empty_like(psi)
+    ex = torch.empty((), dtype=torch.float64, device=dev)
+    plan.workspace(s.n_orb)
+    plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)  # builds the schedule
+    torch.cuda.synchronize()
+    E0, K0 = ex.item(), kpsi.cpu().numpy()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.compute(psi, occ, "energy_kpsi", kpsi=kpsi, ex_out=ex)
+    for rep in range(3):
+        kpsi.fill_(float("nan"))
+        ex.fill_(7.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert ex.item() == E0
+        assert np.array_equal(kpsi.cpu().numpy(), K0)
+        x = torch.randn(1 << 20, device=dev)
+        (x * 2).sum().item()
