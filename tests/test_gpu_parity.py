@@ -36,6 +36,8 @@ CASES = [
     ("wire", 32, 7, 40, 0),
     ("wire", 48, 3, 41, 0),
     ("wire", 64, 3, 42, 0),
+    ("wire", 96, 3, 43, 0),
+    ("periodic", 96, 2, 44, 0),
 ]
 
 
@@ -123,7 +125,7 @@ def test_workspace_too_small_is_rejected():
 # inverse y columns) from n = 112 on; n = 96 runs the 768-thread shared-y block;
 # the FP64 fused path stops at n = 96.
 SPLIT_CASES = [("free", 96, 3, 34, 0), ("free", 112, 2, 35, 0), ("surface", 112, 3, 36, 0),
-               ("free", 128, 2, 38, 0)]
+               ("free", 128, 2, 38, 0), ("wire", 112, 2, 37, 0), ("wire", 128, 2, 39, 0)]
 
 
 @pytest.mark.parametrize("case", SPLIT_CASES, ids=lambda c: f"{c[0]}{c[1]}_N{c[2]}")
