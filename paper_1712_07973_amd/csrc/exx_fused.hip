@@ -568,35 +568,77 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
           }
         }
       }
-#pragma unroll
-      for (int cz = 0; cz < CZ; ++cz) {
-        cpx<T>* B = cz ? Vb : U;  // class cz works in its own buffer
+      if constexpr (N <= 80) {
+        // both z classes side by side, class 0 in U and class 1 in Vb: each phase
+        // holds two independent items per thread (measured at n = 64: pass B
+        // 1.16 -> 1.12 ms; n = 80 4.05 -> 3.79 ms; at n = 96 the registers spill)
+        __syncthreads();  // every yv read of Vb precedes class 1's writes to it
 #pragma unroll
         for (int ii = 0; ii < I1; ++ii) {
           int it = tid + ii * NT;
           if (F::ok1(it)) {
             int ky = it % N, t = it / N;
-            cpx<T> v[L1];
+            cpx<T> v0[L1], v1[L1];
 #pragma unroll
-            for (int k1 = 0; k1 < L1; ++k1)
-              v[k1] = cz ? cmul(yv[ii][k1], md[t + L2 * k1]) : yv[ii][k1];
-            F::z_fwd1_item(v, B, tw, ky, t);
+            for (int k1 = 0; k1 < L1; ++k1) {
+              v0[k1] = yv[ii][k1];
+              v1[k1] = cmul(yv[ii][k1], md[t + L2 * k1]);
+            }
+            F::z_fwd1_item(v0, U, tw, ky, t);
+            F::z_fwd1_item(v1, Vb, tw, ky, t);
           }
         }
         __syncthreads();
-        F::template z_mid<EONLY, MY, MZ>(B, tw, kt, cy, cz, esum, tid);
+        F::template z_mid<EONLY, MY, MZ>(U, tw, kt, cy, 0, esum, tid);
+        F::template z_mid<EONLY, MY, MZ>(Vb, tw, kt, cy, 1, esum, tid);
         __syncthreads();
-        if (EONLY) continue;
+        if (!EONLY) {
 #pragma unroll
-        for (int ii = 0; ii < I1; ++ii) {
-          int it = tid + ii * NT;
-          if (F::ok1(it)) {
-            int ky = it % N, t = it / N;
-            cpx<T> v[L1];
-            F::z_inv1_item(v, B, ky, t);
+          for (int ii = 0; ii < I1; ++ii) {
+            int it = tid + ii * NT;
+            if (F::ok1(it)) {
+              int ky = it % N, t = it / N;
+              cpx<T> v0[L1], v1[L1];
+              F::z_inv1_item(v0, U, ky, t);
+              F::z_inv1_item(v1, Vb, ky, t);
 #pragma unroll
-            for (int k1 = 0; k1 < L1; ++k1)
-              wacc[ii][k1] = cadd(wacc[ii][k1], cz ? cmulc(v[k1], md[t + L2 * k1]) : v[k1]);
+              for (int k1 = 0; k1 < L1; ++k1)
+                wacc[ii][k1] = cadd(cadd(wacc[ii][k1], v0[k1]), cmulc(v1[k1], md[t + L2 * k1]));
+            }
+          }
+          __syncthreads();  // the inverse z steps' reads of U precede its rewrite below
+        }
+      } else {
+#pragma unroll
+        for (int cz = 0; cz < CZ; ++cz) {
+          cpx<T>* B = cz ? Vb : U;  // class cz works in its own buffer
+#pragma unroll
+          for (int ii = 0; ii < I1; ++ii) {
+            int it = tid + ii * NT;
+            if (F::ok1(it)) {
+              int ky = it % N, t = it / N;
+              cpx<T> v[L1];
+#pragma unroll
+              for (int k1 = 0; k1 < L1; ++k1)
+                v[k1] = cz ? cmul(yv[ii][k1], md[t + L2 * k1]) : yv[ii][k1];
+              F::z_fwd1_item(v, B, tw, ky, t);
+            }
+          }
+          __syncthreads();
+          F::template z_mid<EONLY, MY, MZ>(B, tw, kt, cy, cz, esum, tid);
+          __syncthreads();
+          if (EONLY) continue;
+#pragma unroll
+          for (int ii = 0; ii < I1; ++ii) {
+            int it = tid + ii * NT;
+            if (F::ok1(it)) {
+              int ky = it % N, t = it / N;
+              cpx<T> v[L1];
+              F::z_inv1_item(v, B, ky, t);
+#pragma unroll
+              for (int k1 = 0; k1 < L1; ++k1)
+                wacc[ii][k1] = cadd(wacc[ii][k1], cz ? cmulc(v[k1], md[t + L2 * k1]) : v[k1]);
+            }
           }
         }
       }
@@ -608,6 +650,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
         continue;
       }
       // U was last read by the cz = 0 inverse step, before the previous barrier
+      // (the interleaved form: before the barrier that closes its inverse steps)
 #pragma unroll
       for (int ii = 0; ii < I1; ++ii) {
         int it = tid + ii * NT;
