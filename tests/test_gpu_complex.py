@@ -182,3 +182,22 @@ def test_spin_polarized_complex_batch(use_graph):
         for ex, kp in outs:  # clobber the outputs between replays
             kp.fill_(3.0)
             ex.fill_(7.0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused"])
+def test_complex_orbitals_with_the_screened_kernel(precision):
+    # the kernel is independent of the orbitals' type: erfc(omega r)/r on a
+    # periodic grid with complex orbitals
+    say(f"[complex screened] {precision}")
+    import oracle
+    from gpu_common import small_system
+    s = small_system("periodic", 32, 6, 74, kmax=KMAX)
+    omega = 0.4
+    ref = oracle.exx(s.psi, s.occ, s.h, "periodic", omega=omega, symmetric=True)
+    psi, occ = tensors(s)
+    g = exx.Grid(n=s.n, h=s.h, bc="periodic", kernel="screened", omega=omega)
+    plan = exx.Plan(g, precision, n_orb_max=s.n_orb, complex_orbitals=True)
+    pe = torch.empty((s.n_orb, s.n_orb), dtype=torch.float64, device=psi.device)
+    ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)
+    torch.cuda.synchronize()
+    check(precision, s, ref, float(ex.item()), kpsi.cpu().numpy(), pe.cpu().numpy())
