@@ -41,9 +41,11 @@ __device__ __forceinline__ int fold(int k, int M) { return k <= M - k ? k : M - 
 // z-block of the spectrum layout; passes A and C move one z-block of rows
 constexpr int XZ = 16;
 
-#ifndef PASS_A_SLOTS
-#define PASS_A_SLOTS 2  // slots per pass A block
-#endif
+// slots per pass A block.  With the non-temporal spectrum stores, up to n = 64 more
+// blocks beat reusing a block's set-up (64^3, 32 orbitals: pass A 0.178 ms with one
+// slot, 0.212 with 2, 0.219 with 4); larger grids already launch enough blocks per
+// slot and gain from two (16 free grids of n = 48..112: 614 against 625 ms).
+constexpr int pass_a_slots(int n) { return n <= 64 ? 1 : 2; }
 
 // offset of (cx, kx, y, z) within a slot, and of (y, z) within slab (cx, kx)
 template <int N, int NCLS>
@@ -1693,7 +1695,7 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
     constexpr int ZB = XZ;
     constexpr int NT = 256;
-    constexpr int SPB = PASS_A_SLOTS;
+    constexpr int SPB = pass_a_slots(N);
     dim3 grid(N * (N / ZB), (nslots + SPB - 1) / SPB);
     auto* Xc = static_cast<cpx<T>*>(X);
     auto* tw = static_cast<const cpx<T>*>(tb.tw);
