@@ -715,7 +715,7 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
   }
 
   if (EONLY) {
-    // block reduction of the Parseval sum, one atomic per block
+    // block reduction of the Parseval sum into this (slot, slab)'s partial
     __shared__ double red[NT / 64];
     double v = esum;
 #pragma unroll
