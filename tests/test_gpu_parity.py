@@ -164,3 +164,27 @@ def test_kpsi_output_is_overwritten(bc, precision, kmax):
         assert np.all(np.isfinite(K))
         tol = TOL_FP32_K if precision == "fp32" else TOL_FP64_K
         assert kpsi_rel_err(K, ref["kpsi"]) < tol
+
+
+def test_fp32_odd_slot_chunks_above_n64():
+    # Above n = 64 a pass A block takes two consecutive slots; launch chunks of
+    # 5 slots from tiles of 3 (9 pairs, 5 packed slots per off-diagonal tile
+    # pair) leave a one-slot last block in every launch.
+    bc, n, N, seed = "free", 80, 7, 45
+    say(f"[parity chunks] fp32 {bc} n={n} N={N} seed={seed} tile=3 batch_slots=5")
+    s, ref = oracle_result(bc, n, N, seed, 0)
+    dev = torch.device("cuda", 0)
+    plan = exx.Plan(grid_of(s), "fp32", n_orb_max=N)
+    plan.set_tuning(tile=3, batch_slots=5)
+    assert plan.tuning["tile"] == 3
+    plan.enable_profiling(True)
+    plan.read_profile()
+    pe = torch.empty((N, N), dtype=torch.float64, device=dev)
+    ex, kp, pe = plan.compute(torch.from_numpy(s.psi).to(dev), torch.from_numpy(s.occ).to(dev),
+                              "energy_kpsi", pair_e=pe)
+    torch.cuda.synchronize()
+    assert plan.read_profile()["pass_a"][1] > 1
+    assert abs(ex.item() - ref["E"]) / N < TOL_FP32_E_PER_ORB
+    assert kpsi_rel_err(kp.cpu().numpy(), ref["kpsi"]) < TOL_FP32_K
+    P = pe.cpu().numpy()
+    assert np.max(np.abs(P - ref["pair_e"])) <= 1e-6 * np.max(np.abs(ref["pair_e"]))
