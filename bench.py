@@ -318,6 +318,8 @@ def main(argv=None) -> int:
     ap.add_argument("--tile", type=int, default=0, help="pair-tile edge (0: plan default)")
     ap.add_argument("--batch-slots", type=int, default=0,
                     help="slots per launch chunk (0: plan default)")
+    ap.add_argument("--slab-form", default="0", choices=["0", "shared", "wave"],
+                    help="form of the y/z pass (0: plan default)")
     ap.add_argument("--streams", type=int, default=0,
                     help="1: serial passes, 3: overlapped rounds (0: plan default)")
     ap.add_argument("--graph", action="store_true",
@@ -367,7 +369,7 @@ def main(argv=None) -> int:
 
     plan = exx.Plan(grid, "fp32", n_orb_max=N, complex_orbitals=cplx)
     plan.set_tuning(tile=a.tile, slab_threads=a.slab_threads, batch_slots=a.batch_slots,
-                    streams=a.streams)
+                    streams=a.streams, slab_form=0 if a.slab_form == "0" else a.slab_form)
     plan.workspace(N)
     _, n_slots = plan.schedule_info(N)
     ms, wall, prof = timed(plan, psi, occ, kpsi, ex, a.steps, a.warmup, use_graph=a.graph)

@@ -176,7 +176,17 @@ typedef struct exx_tuning {
                        3: per round of pair tiles, the pair-build pass, the y/z pass and the
                        reduction pass run on three streams, so that the memory-bound passes
                        of one round overlap the y/z pass of another (fused paths only) */
+  int slab_form;    /* enum exx_slab_form: how the y/z pass works through a slab */
 } exx_tuning;
+
+/* Forms of the y/z pass (exx_tuning.slab_form).
+ *   SHARED: the workgroup shares every line exchange through LDS behind
+ *           workgroup barriers (two slab buffers where they fit, else three
+ *           launches through a scratch of y-transformed slabs);
+ *   WAVE  : one slab buffer; a wavefront owns whole lines in each phase, so line
+ *           exchanges synchronise one wavefront only and two workgroup barriers
+ *           per y class remain (FP32: every n; FP64_FUSED: n <= 80). */
+enum exx_slab_form { EXX_SLAB_SHARED = 1, EXX_SLAB_WAVE = 2 };
 
 int exx_plan_get_tuning(const exx_plan* plan, exx_tuning* out);
 int exx_plan_set_tuning(exx_plan* plan, const exx_tuning* t);

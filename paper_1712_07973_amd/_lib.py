@@ -35,7 +35,10 @@ class ExxGrid(C.Structure):
 
 class ExxTuning(C.Structure):
     _fields_ = [("tile", C.c_int), ("batch_slots", C.c_int), ("slab_threads", C.c_int),
-                ("streams", C.c_int)]
+                ("streams", C.c_int), ("slab_form", C.c_int)]
+
+
+SLAB_FORMS = {"shared": 1, "wave": 2}
 
 
 PASS_KINDS = ["convert", "zero", "pass_a", "pass_b", "pass_c", "finalize", "plain_fft",

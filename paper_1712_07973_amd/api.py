@@ -142,13 +142,16 @@ class Plan:
     def tuning(self) -> dict:
         t = L.ExxTuning()
         L.check(L.lib().exx_plan_get_tuning(self._h, C.byref(t)), "exx_plan_get_tuning")
+        forms = {v: k for k, v in L.SLAB_FORMS.items()}
         return {"tile": t.tile, "batch_slots": t.batch_slots, "slab_threads": t.slab_threads,
-                "streams": t.streams}
+                "streams": t.streams, "slab_form": forms.get(t.slab_form, t.slab_form)}
 
     def set_tuning(self, tile: int = 0, batch_slots: int = 0, slab_threads: int = 0,
-                   streams: int = 0) -> None:
-        """0 keeps a field; streams is 1 (serial passes) or 3 (overlapped rounds)."""
-        t = L.ExxTuning(int(tile), int(batch_slots), int(slab_threads), int(streams))
+                   streams: int = 0, slab_form=0) -> None:
+        """0 keeps a field; streams is 1 (serial passes) or 3 (overlapped rounds);
+        slab_form is "shared" or "wave" (the y/z pass form, see exx.h)."""
+        form = L.SLAB_FORMS[slab_form] if isinstance(slab_form, str) else int(slab_form)
+        t = L.ExxTuning(int(tile), int(batch_slots), int(slab_threads), int(streams), form)
         L.check(L.lib().exx_plan_set_tuning(self._h, C.byref(t)), "exx_plan_set_tuning")
 
     def enable_profiling(self, on: bool = True) -> None:

@@ -151,6 +151,10 @@ void default_tuning(exx_plan* p) {
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
   p->tuning.slab_threads = (p->n == 64 && is_fp32(p)) ? 512 : 256;
   p->tuning.streams = 1;
+  p->tuning.slab_form = !is_plain(p) && pass_b_wave_supported(p->precision, p->n) &&
+                                is_fp32(p)
+                            ? EXX_SLAB_WAVE
+                            : EXX_SLAB_SHARED;
 }
 
 int schedule_tile(const exx_plan* p) {
@@ -173,7 +177,9 @@ struct WsLayout {
   int split_slots = 0;  // slots per launch of the split pass B (0: not split)
 };
 
-bool uses_split(const exx_plan* p) { return pass_b_split(p->precision, p->n, p->ncls, p->cy, p->cz); }
+bool uses_split(const exx_plan* p) {
+  return p->tuning.slab_form != EXX_SLAB_WAVE && pass_b_split(p->precision, p->n, p->ncls, p->cy, p->cz);
+}
 
 // bytes per slot of the split pass B scratch: ncls cy n^3 complex FP32
 size_t split_slot_bytes(const exx_plan* p) { return (size_t)p->ncls * p->cy * p->n * p->n * p->n * 8; }
@@ -311,7 +317,8 @@ int run_fused(exx_plan* p, const Schedule& s, const WsLayout& w, const double* p
   auto pass_b = [&](const Launch& Lb, char* Xs, int s0, int ns) -> int {
     if (w.split_slots == 0) {
       EXX_PROF_ON(EXX_PASS_B, Lb.stream);
-      EXX_HIP(launch_pass_b<T>(Lb, Xs, ns, parseval, e_part, s0, p->tables, p->tuning.slab_threads));
+      EXX_HIP(launch_pass_b<T>(Lb, Xs, ns, parseval, e_part, s0, p->tables, p->tuning.slab_threads,
+                               p->tuning.slab_form));
       return EXX_OK;
     }
     if constexpr (sizeof(T) == 4) {
@@ -657,10 +664,15 @@ int exx_plan_set_tuning(exx_plan* p, const exx_tuning* t) {
     return fail(EXX_ERR_INVALID_ARG, "slab_threads must be 256 or 512");
   if (t->streams != 0 && t->streams != 1 && t->streams != 3)
     return fail(EXX_ERR_INVALID_ARG, "streams must be 1 or 3");
+  if (t->slab_form != 0 && t->slab_form != EXX_SLAB_SHARED && t->slab_form != EXX_SLAB_WAVE)
+    return fail(EXX_ERR_INVALID_ARG, "slab_form must be EXX_SLAB_SHARED (1) or EXX_SLAB_WAVE (2)");
+  if (t->slab_form == EXX_SLAB_WAVE && (is_plain(p) || !pass_b_wave_supported(p->precision, p->n)))
+    return fail(EXX_ERR_INVALID_ARG, "the wave-local y/z pass does not fit this grid and precision");
   if (t->tile) p->tuning.tile = t->tile;
   if (t->batch_slots) p->tuning.batch_slots = t->batch_slots;
   if (t->slab_threads) p->tuning.slab_threads = t->slab_threads;
   if (t->streams) p->tuning.streams = t->streams;
+  if (t->slab_form) p->tuning.slab_form = t->slab_form;
   return EXX_OK;
 }
 

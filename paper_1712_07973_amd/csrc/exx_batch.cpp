@@ -234,8 +234,8 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
       auto bar = line.find('|');
       if (bar == std::string::npos || line.substr(0, bar) != key.str()) continue;
       exx_tuning t{};
-      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d", &t.tile, &t.batch_slots,
-                      &t.slab_threads, &t.streams) == 4)
+      if (std::sscanf(line.c_str() + bar + 1, "%d %d %d %d %d", &t.tile, &t.batch_slots,
+                      &t.slab_threads, &t.streams, &t.slab_form) == 5)
         return exx_plan_set_tuning(p, &t);
     }
   }
@@ -253,6 +253,25 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
                                       ? std::vector<int>{256, 512}
                                       : std::vector<int>{p->tuning.slab_threads};
   std::vector<int> streams = fused ? std::vector<int>{1, 3} : std::vector<int>{1};
+  // y/z pass forms: the workgroup-shared one always, the wave-local one where it fits
+  std::vector<int> forms = {EXX_SLAB_SHARED};
+  if (fused && exx::pass_b_wave_supported(p->precision, p->n)) forms.push_back(EXX_SLAB_WAVE);
+  std::vector<exx_tuning> cands;
+  for (int t : tiles)
+    for (int bs : batches)
+      for (int form : forms)
+        for (int sth : slab_threads) {
+          if (form == EXX_SLAB_WAVE && sth != slab_threads.front()) continue;  // no thread choice
+          for (int nst : streams) {
+            exx_tuning cand = base;
+            cand.tile = t;
+            cand.batch_slots = bs;
+            cand.slab_threads = sth;
+            cand.streams = nst;
+            cand.slab_form = form;
+            cands.push_back(cand);
+          }
+        }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   double* ex_dev = nullptr;
   hipError_t he = hipEventCreate(&e0);
@@ -264,40 +283,27 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
     return record_hip_error(he, "autotune events / scratch scalar");
   }
   int rc = EXX_OK;
-  for (int t : tiles) {
-    for (int bs : batches) {
-     for (int sth : slab_threads) {
-      for (int nst : streams) {
-      if (best_ms < 1e30f && spent()) continue;  // budget spent: keep the best so far
-      exx_tuning cand = base;
-      cand.tile = t;
-      cand.batch_slots = bs;
-      cand.slab_threads = sth;
-      cand.streams = nst;
-      if (exx_plan_set_tuning(p, &cand) != EXX_OK) continue;
-      size_t need = 0;
-      if (exx_workspace_bytes(p, n_orb, &need) != EXX_OK || need > ws_bytes) continue;
-      if (exx_plan_prepare(p, n_orb) != EXX_OK) continue;
-      rc = exx_compute(p, psi, occ, n_orb, EXX_MODE_ENERGY_KPSI, 0, ex_dev, kpsi, nullptr, ws, ws_bytes, st);
-      if (rc != EXX_OK) break;
-      (void)hipEventRecord(e0, st);
-      const int reps = 3;
-      for (int r = 0; r < reps && rc == EXX_OK; ++r)
-        rc = exx_compute(p, psi, occ, n_orb, EXX_MODE_ENERGY_KPSI, 0, ex_dev, kpsi, nullptr, ws, ws_bytes, st);
-      (void)hipEventRecord(e1, st);
-      (void)hipEventSynchronize(e1);
-      float ms = 0;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (rc == EXX_OK && ms < best_ms) {
-        best_ms = ms;
-        best = cand;
-      }
-      }
-      if (rc != EXX_OK) break;
-     }
-     if (rc != EXX_OK) break;
-    }
+  for (const exx_tuning& cand : cands) {
+    if (best_ms < 1e30f && spent()) break;  // budget spent: keep the best so far
+    if (exx_plan_set_tuning(p, &cand) != EXX_OK) continue;
+    size_t need = 0;
+    if (exx_workspace_bytes(p, n_orb, &need) != EXX_OK || need > ws_bytes) continue;
+    if (exx_plan_prepare(p, n_orb) != EXX_OK) continue;
+    rc = exx_compute(p, psi, occ, n_orb, EXX_MODE_ENERGY_KPSI, 0, ex_dev, kpsi, nullptr, ws, ws_bytes, st);
     if (rc != EXX_OK) break;
+    (void)hipEventRecord(e0, st);
+    const int reps = 3;
+    for (int r = 0; r < reps && rc == EXX_OK; ++r)
+      rc = exx_compute(p, psi, occ, n_orb, EXX_MODE_ENERGY_KPSI, 0, ex_dev, kpsi, nullptr, ws, ws_bytes, st);
+    (void)hipEventRecord(e1, st);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rc != EXX_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = cand;
+    }
   }
   (void)hipFree(ex_dev);
   (void)hipEventDestroy(e0);
@@ -307,7 +313,7 @@ int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, d
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
     f << key.str() << "|" << best.tile << " " << best.batch_slots << " " << best.slab_threads
-      << " " << best.streams << "\n";
+      << " " << best.streams << " " << best.slab_form << "\n";
   }
   return exx_plan_prepare(p, n_orb);
 }

@@ -744,6 +744,361 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
 }
 
 // ---------------------------------------------------------------------------
+// pass B, wave-local form.  One slab (slot, cx, kx) per workgroup of 8 N
+// threads (N / 8 wavefronts).  Every n-point line transform is two register
+// steps, DFT_{N/8} per lane over points t + 8 k1 and DFT_8 across the line's 8
+// lanes, with one LDS exchange between them.  The 8 lanes of a line sit in one
+// wavefront, and a wavefront owns 8 whole columns of the slab while it
+// transforms along y and 8 whole rows while it transforms along z, so inside a
+// phase every exchange stays within one wavefront: it synchronises with itself
+// only (the LDS operations of a wavefront take effect in issue order).  Only
+// the two transpositions per y class, columns -> rows before the z phase and
+// rows -> columns after it, need a workgroup barrier.
+//
+// Per y class cy: forward y (columns), then per z class cz the forward z
+// transform of the y-transformed rows (modulated by w_2n^z for cz = 1), the
+// kernel multiply (or the Parseval sum), the inverse z transform and the
+// demodulated sum over cz (rows), then the inverse y transform, demodulated
+// (columns).  With two y classes the class-0 result waits in HBM-backed global
+// memory (the slab itself, after its class-1 input has been read) or, for
+// small slabs, in registers; the class-1 result is added to it.
+//
+// LDS: one slab buffer, row pitch PB, element (row, col) at row PB + col +
+// col / 8 (one spare word per 8 columns spreads a row's stride-8 accesses over
+// the banks), PB = 8 mod 16 (so rows an odd number of rows apart, or two rows
+// apart, fall on different bank halves).  Within the y phase the values
+// between the two steps sit at row p ^ ((p / 8) & 3) of their column instead
+// of row p = t + 8 q1, which keeps both steps' accesses free of bank conflicts.
+// ---------------------------------------------------------------------------
+template <int N>
+constexpr int wave_pitch() {
+  int p = 9 * N / 8;
+  while (p % 16 != 8) ++p;
+  return p;
+}
+
+// The two-class output of the y classes is held in registers (instead of being
+// parked in the slab) while a thread's value count stays small.
+template <typename T, int N>
+constexpr bool wave_hold_p0() {
+  return sizeof(T) == 4 && N <= 64;
+}
+
+// A value the compiler must treat as unknown from here on: keeps it from
+// carrying addresses computed in one phase over to the next (their registers
+// would stay live, and spill, across the phases in between).
+__device__ __forceinline__ unsigned opaque(unsigned v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Vector loads of one complex value through a buffer resource: a lane's byte
+// offset in a register, a block-uniform offset in a scalar register, so the
+// rows of a column share one address register.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> buffer_load_cpx(__amdgpu_buffer_rsrc_t r, unsigned voff,
+                                                  unsigned soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  // orders this wavefront's LDS accesses before and after this point (the
+  // hardware keeps a wavefront's LDS operations in order; the fences keep the
+  // compiler from moving accesses across)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One y class of the wave-local pass B (CYI = 0 or 1, compile time).  P holds
+// the class-0 output of this lane's column points between the classes.
+template <typename T, int N, int CX, int CY, int CZ, bool EONLY, int CYI>
+__device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T>* __restrict__ tw,
+                                             const cpx<T>* __restrict__ md, cpx<T>* g,
+                                             __amdgpu_buffer_rsrc_t grs, const T* kt,
+                                             cpx<T> (&P)[N / 8], double& esum) {
+  constexpr int L1 = N / 8, PB = wave_pitch<N>();
+  constexpr int NJ = (L1 + 7) / 8;  // step-2 items per lane
+  constexpr int MY = CY * N, MZ = CZ * N;
+  constexpr int HZ = MZ / 2 + 1;
+  constexpr bool PADY = CY == 2, PADZ = CZ == 2;
+  constexpr bool HOLD = wave_hold_p0<T, N>();
+  constexpr unsigned KSTRIDE = 8u * CX * N * N * sizeof(cpx<T>);  // slab rows y -> y + 8
+
+  // lane coordinates, laundered per class (see opaque)
+  const unsigned tid = opaque(threadIdx.x);
+  const int lane = tid & 63, wv = tid >> 6;
+  // column phases: column zc, position ty; row phase: row kr, position tz
+  const int zc = 8 * wv + (lane & 7), ty = lane >> 3;
+  cpx<T>* Scol = S + (zc + (zc >> 3));
+  const int kr = 8 * wv + (lane >> 3), tz = lane & 7;
+  cpx<T>* Srow = S + kr * PB;
+  // slab element (ty + 8 k1, zc): this lane's byte offset plus k1 KSTRIDE
+  // (a slab spans less than CX N^3 values of one slot: 32-bit offsets)
+  const unsigned goff = (unsigned)(((size_t)ty * CX * N * N + (size_t)(zc / XZ) * (CX * N * XZ) +
+                                    zc % XZ) * sizeof(cpx<T>));
+  auto gat = [&](int k1) -> cpx<T>* {
+    return reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(g) + goff + (size_t)k1 * KSTRIDE);
+  };
+
+  // ---- forward y, step 1: DFT_L1 over y = ty + 8 k1 of column zc
+  {
+    cpx<T> v[L1];
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) {
+      const cpx<T> a = buffer_load_cpx<T>(grs, goff, k1 * KSTRIDE);
+      v[k1] = CYI ? cmul(a, md[ty + 8 * k1]) : a;
+    }
+    if constexpr (CYI == 1 && !EONLY && !HOLD) {
+      // the class-1 input is in registers: park the class-0 output in the slab
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) *gat(k1) = P[k1];
+    }
+    Dft<L1, -1, T>::run(v);
+#pragma unroll
+    for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[q1 * 8 + ty]);
+#pragma unroll
+    for (int q1 = 0; q1 < L1; ++q1) Scol[((ty ^ (q1 & 3)) + 8 * q1) * PB] = v[q1];
+  }
+  wave_lds_sync();
+  // ---- forward y, step 2: DFT_8 over t for q1 = ty + 8 j -> ky = q1 + L1 q2
+  {
+    cpx<T> w[NJ][8];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int q1 = ty + 8 * j;
+      if (q1 < L1) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) w[j][t] = Scol[((t ^ (ty & 3)) + 8 * q1) * PB];
+      }
+    }
+    wave_lds_sync();  // every lane's reads precede the in-place writes
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int q1 = ty + 8 * j;
+      if (q1 < L1) {
+        Dft<8, -1, T>::run(w[j]);
+#pragma unroll
+        for (int q2 = 0; q2 < 8; ++q2) Scol[(q1 + L1 * q2) * PB] = w[j][q2];
+      }
+    }
+  }
+  __syncthreads();  // columns -> rows
+
+  // ---- z phase on row kr (ky): values z = tz + 8 k1 at column tz + 9 k1.
+  // Both z classes take their forward step 1 from the row at once; class 1's
+  // result waits in registers while class 0 finishes in the row.
+  {
+    const int kyf = PADY ? 2 * kr + CYI : kr;
+    const T* krow = kt + (size_t)fold(kyf, MY) * HZ;
+    // step 2 of one class, in place in the row: per q1 = tz + 8 j, DFT_8,
+    // kernel (kz = q1 + L1 q2) or the Parseval sum, inverse DFT_8
+    auto z_mid = [&](int cz) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int q1 = tz + 8 * j;
+        if (q1 < L1) {
+          cpx<T> w[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) w[t] = Srow[t + 9 * q1];
+          Dft<8, -1, T>::run(w);
+          // kernel index kzf = c + step q2: below half the range fold(kzf) = kzf,
+          // above it MZ - kzf, switching exactly at q2 = 4
+          constexpr int step = PADZ ? 2 * L1 : L1;
+          const int c = PADZ ? 2 * q1 + cz : q1;
+          const T* k_lo = krow + c;
+          const T* k_hi = krow + (MZ - c);
+#pragma unroll
+          for (int q2 = 0; q2 < 8; ++q2) {
+            const T kv = (q2 < 4) ? k_lo[step * q2] : k_hi[-step * q2];
+            if (EONLY) {
+              esum += (double)kv * ((double)w[q2].x * (double)w[q2].x +
+                                    (double)w[q2].y * (double)w[q2].y);
+            } else {
+              w[q2].x *= kv;
+              w[q2].y *= kv;
+            }
+          }
+          if (!EONLY) {
+            Dft<8, 1, T>::run(w);
+#pragma unroll
+            for (int t = 1; t < 8; ++t) w[t] = cmulc(w[t], tw[q1 * 8 + t]);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) Srow[t + 9 * q1] = w[t];
+          }
+        }
+      }
+    };
+    cpx<T> u1[CZ == 2 ? L1 : 1];
+    {
+      cpx<T> u0[L1];
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        u0[k1] = Srow[tz + 9 * k1];
+        if constexpr (CZ == 2) u1[k1] = cmul(u0[k1], md[tz + 8 * k1]);
+      }
+      Dft<L1, -1, T>::run(u0);
+#pragma unroll
+      for (int q1 = 1; q1 < L1; ++q1) u0[q1] = cmul(u0[q1], tw[q1 * 8 + tz]);
+#pragma unroll
+      for (int q1 = 0; q1 < L1; ++q1) Srow[tz + 9 * q1] = u0[q1];
+    }
+    if constexpr (CZ == 2) {
+      Dft<L1, -1, T>::run(u1);
+#pragma unroll
+      for (int q1 = 1; q1 < L1; ++q1) u1[q1] = cmul(u1[q1], tw[q1 * 8 + tz]);
+    }
+    wave_lds_sync();
+    z_mid(0);
+    wave_lds_sync();  // step 2 of class 0 precedes the reads and stores below
+    cpx<T> acc[L1];
+    if constexpr (!EONLY) {
+      // inverse step 1 of class 0: IDFT_L1 over q1 -> z = tz + 8 k1
+#pragma unroll
+      for (int q1 = 0; q1 < L1; ++q1) acc[q1] = Srow[tz + 9 * q1];
+      Dft<L1, 1, T>::run(acc);
+    }
+    if constexpr (CZ == 2) {
+      // class 1 into the row (this lane's own step-1 addresses)
+#pragma unroll
+      for (int q1 = 0; q1 < L1; ++q1) Srow[tz + 9 * q1] = u1[q1];
+      wave_lds_sync();
+      z_mid(1);
+      wave_lds_sync();
+      if constexpr (!EONLY) {
+        cpx<T> v[L1];
+#pragma unroll
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = Srow[tz + 9 * q1];
+        Dft<L1, 1, T>::run(v);
+#pragma unroll
+        for (int k1 = 0; k1 < L1; ++k1) acc[k1] = cadd(acc[k1], cmulc(v[k1], md[tz + 8 * k1]));
+      }
+    }
+    if constexpr (EONLY) {
+      __syncthreads();  // rows -> columns: the next class rewrites every column
+      return;
+    } else {
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) Srow[tz + 9 * k1] = acc[k1];
+    }
+  }
+  __syncthreads();  // rows -> columns
+
+  // ---- inverse y (column zc again), step 2: IDFT_8 over q2 (ky = q1 + L1 q2),
+  // conjugate twiddle; lane coordinates laundered again for this phase
+  const unsigned tid2 = opaque(threadIdx.x);
+  const int zc2 = 8 * (int)(tid2 >> 6) + (int)(tid2 & 7), ty2 = (int)((tid2 & 63) >> 3);
+  cpx<T>* Scol2 = S + (zc2 + (zc2 >> 3));
+  {
+    cpx<T> w[NJ][8];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int q1 = ty2 + 8 * j;
+      if (q1 < L1) {
+#pragma unroll
+        for (int q2 = 0; q2 < 8; ++q2) w[j][q2] = Scol2[(q1 + L1 * q2) * PB];
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int q1 = ty2 + 8 * j;
+      if (q1 < L1) {
+        Dft<8, 1, T>::run(w[j]);
+#pragma unroll
+        for (int t = 1; t < 8; ++t) w[j][t] = cmulc(w[j][t], tw[q1 * 8 + t]);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) Scol2[((t ^ (ty2 & 3)) + 8 * q1) * PB] = w[j][t];
+      }
+    }
+  }
+  wave_lds_sync();
+  // ---- inverse y, step 1: IDFT_L1 over q1 -> y = ty + 8 k1, demodulate
+  {
+    cpx<T> o[L1];
+#pragma unroll
+    for (int q1 = 0; q1 < L1; ++q1) o[q1] = Scol2[((ty2 ^ (q1 & 3)) + 8 * q1) * PB];
+    Dft<L1, 1, T>::run(o);
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) o[k1] = CYI ? cmulc(o[k1], md[ty2 + 8 * k1]) : o[k1];
+    if constexpr (CY == 2 && CYI == 0) {
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) P[k1] = o[k1];
+    } else {
+      const unsigned off = (unsigned)(((size_t)ty2 * CX * N * N + (size_t)(zc2 / XZ) * (CX * N * XZ) +
+                                       zc2 % XZ) * sizeof(cpx<T>));
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) {
+        cpx<T>* dst = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(g) + off + (size_t)k1 * KSTRIDE);
+        if (CY == 2) o[k1] = cadd(o[k1], HOLD ? P[k1] : *dst);
+        *dst = o[k1];
+      }
+    }
+  }
+  // the next class's forward y stores go to this wavefront's own columns
+  wave_lds_sync();
+}
+
+template <typename T, int N, int CX, int CY, int CZ, bool EONLY>
+__global__ __launch_bounds__(8 * N) void k_pass_b_wave(cpx<T>* __restrict__ X,
+                                                       const T* __restrict__ ktab,
+                                                       const cpx<T>* __restrict__ twg,
+                                                       const cpx<T>* __restrict__ mdg,
+                                                       double* __restrict__ e_slot, int slot0,
+                                                       int kparts) {
+  constexpr int NT = 8 * N, L1 = N / 8, PB = wave_pitch<N>();
+  constexpr int MX = CX * N, MY = CY * N, MZ = CZ * N;
+  constexpr int HY = MY / 2 + 1, HZ = MZ / 2 + 1;
+  constexpr bool ANY_PAD = CX == 2 || CY == 2 || CZ == 2;
+  static_assert(N % 8 == 0 && L1 <= 16, "line length 8 L1 with L1 <= 16");
+  __shared__ cpx<T> S[N * PB];
+  __shared__ cpx<T> tw[L1 * 8];  // tw[q1 8 + t] = w_N^{t q1}: a lane's twiddles are one base plus constants
+  __shared__ cpx<T> md[N];
+
+  const int tid = threadIdx.x;
+  const int slab = blockIdx.x;  // cx * N + kx
+  const int ls = blockIdx.y;
+  const int cx = slab / N, kxp = slab % N;
+  const int kxf = CX == 2 ? 2 * kxp + cx : kxp;
+  const T* kt = ktab + (size_t)fold(kxf, MX) * HY * HZ;
+  cpx<T>* g = X + (size_t)ls * CX * N * N * N + slab_base(slab);
+  const __amdgpu_buffer_rsrc_t grs = buffer_rsrc(g);
+
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[(k & 7) * (k >> 3)];
+    if (ANY_PAD) md[k] = mdg[k];
+  }
+  __syncthreads();
+
+  double esum = 0.0;
+  cpx<T> P[L1];
+  wave_y_class<T, N, CX, CY, CZ, EONLY, 0>(S, tw, md, g, grs, kt, P, esum);
+  if constexpr (CY == 2) wave_y_class<T, N, CX, CY, CZ, EONLY, 1>(S, tw, md, g, grs, kt, P, esum);
+
+  if constexpr (EONLY) {
+    // block reduction of the Parseval sum into this (slot, slab)'s partial
+    __shared__ double red[NT / 64];
+    double v = esum;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double sum = 0.0;
+      for (int w = 0; w < NT / 64; ++w) sum += red[w];
+      e_slot[(size_t)(2 * (slot0 + ls)) * kparts + slab] = sum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pass B split in three launches for slabs whose two LDS buffers do not fit
 // (n >= 112 with a zero-padded z axis).  The 2-D transform of a
 // slab factorises into independent 1-D transforms along y (per z column) and
@@ -1757,9 +2112,46 @@ hipError_t launch_pass_b_cls(const Launch& L, cpx<T>* Xc, int nslots, bool energ
 // with the spectrum's y and z exchanged (passes A and C swap_yz, kernel table
 // [fx][fz][fy]), so that its periodic axis is transformed once for both
 // y classes (6 instead of 8 line sets per slab)
+template <typename T, int N>
+constexpr bool wave_form_fits() {  // one slab buffer plus the tables in LDS
+  return (size_t)N * wave_pitch<N>() * sizeof(cpx<T>) + 2 * N * sizeof(cpx<T>) <= 160 * 1024;
+}
+
+template <typename T, int N, int CX, int CY, int CZ>
+hipError_t launch_pass_b_wave(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
+                              double* e_slot, int slot0, const Tables& tb) {
+  if constexpr (!wave_form_fits<T, N>()) {
+    return hipErrorInvalidValue;
+  } else {
+    auto* kt = static_cast<const T*>(tb.ktab);
+    auto* tw = static_cast<const cpx<T>*>(tb.tw);
+    auto* md = static_cast<const cpx<T>*>(tb.md);
+    dim3 grid(CX * N, nslots);
+    if (energy_only)
+      hipLaunchKernelGGL((k_pass_b_wave<T, N, CX, CY, CZ, true>), grid, dim3(8 * N), 0, L.stream,
+                         Xc, kt, tw, md, e_slot, slot0, energy_parts(N));
+    else
+      hipLaunchKernelGGL((k_pass_b_wave<T, N, CX, CY, CZ, false>), grid, dim3(8 * N), 0, L.stream,
+                         Xc, kt, tw, md, e_slot, slot0, energy_parts(N));
+    return hipGetLastError();
+  }
+}
+
+bool pass_b_wave_supported(int precision, int n) {
+  bool ok = false;
+  (void)dispatch_n(n, [&]<int N>() -> hipError_t {
+    ok = precision == EXX_PREC_FP64_FUSED ? wave_form_fits<double, N>() : wave_form_fits<float, N>();
+    return hipSuccess;
+  });
+  return ok;
+}
+
 template <typename T, int N, int CX, int CY, int CZ>
 hipError_t launch_pass_b_for(const Launch& L, cpx<T>* Xc, int nslots, bool energy_only,
-                             double* e_slot, int slot0, const Tables& tb, int slab_threads) {
+                             double* e_slot, int slot0, const Tables& tb, int slab_threads,
+                             int form) {
+  if (form == EXX_SLAB_WAVE)
+    return launch_pass_b_wave<T, N, CX, CY, CZ>(L, Xc, nslots, energy_only, e_slot, slot0, tb);
   constexpr bool SY = pass_b_share_y<T, N, CY, CZ>();
   constexpr int NT = pass_b_threads<T, N, SY>();
   if constexpr (SY && NT == 256 && sizeof(T) == 4 && N == 64) {
@@ -1774,7 +2166,7 @@ hipError_t launch_pass_b_for(const Launch& L, cpx<T>* Xc, int nslots, bool energ
 
 template <typename T>
 hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
-                         int slot0, const Tables& tb, int slab_threads) {
+                         int slot0, const Tables& tb, int slab_threads, int form) {
   if (nslots <= 0) return hipSuccess;
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
     if constexpr (sizeof(T) == 8 && N > 96) {
@@ -1783,16 +2175,16 @@ hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only,
       auto* Xc = static_cast<cpx<T>*>(X);
       if (L.ncls == 2 && L.cy == 2 && L.cz == 2)
         return launch_pass_b_for<T, N, 2, 2, 2>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
-                                                slab_threads);
+                                                slab_threads, form);
       if (L.ncls == 1 && L.cy == 1 && L.cz == 2)
         return launch_pass_b_for<T, N, 1, 1, 2>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
-                                                slab_threads);
+                                                slab_threads, form);
       if (L.ncls == 1 && L.cy == 1 && L.cz == 1)
         return launch_pass_b_for<T, N, 1, 1, 1>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
-                                                slab_threads);
+                                                slab_threads, form);
       if (L.ncls == 2 && L.cy == 1 && L.cz == 2)  // wire, y and z exchanged
         return launch_pass_b_for<T, N, 2, 1, 2>(L, Xc, nslots, energy_only, e_slot, slot0, tb,
-                                                slab_threads);
+                                                slab_threads, form);
       return hipErrorInvalidValue;
     }
   });
@@ -1926,9 +2318,9 @@ template hipError_t launch_pass_a<float>(const Launch&, const float*, void*, con
 template hipError_t launch_pass_a<double>(const Launch&, const double*, void*, const Slot*, int,
                                           int, const double*, bool, const Tables&);
 template hipError_t launch_pass_b<float>(const Launch&, void*, int, bool, double*, int,
-                                         const Tables&, int);
+                                         const Tables&, int, int);
 template hipError_t launch_pass_b<double>(const Launch&, void*, int, bool, double*, int,
-                                          const Tables&, int);
+                                          const Tables&, int, int);
 template hipError_t launch_pass_b_split<float>(const Launch&, void*, void*, int, bool, double*, int,
                                                const Tables&);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,

@@ -83,7 +83,9 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
                          int nslots, const double* occ, bool weighted, const Tables& tb);
 template <typename T>
 hipError_t launch_pass_b(const Launch& L, void* X, int nslots, bool energy_only, double* e_slot,
-                         int slot0, const Tables& tb, int slab_threads);
+                         int slot0, const Tables& tb, int slab_threads, int form);
+// whether the wave-local y/z pass (EXX_SLAB_WAVE) fits a grid of n points
+bool pass_b_wave_supported(int precision, int n);
 template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,

@@ -51,3 +51,11 @@ def kpsi_rel_err(a: np.ndarray, b: np.ndarray) -> float:
 def grid_of(s):
     import paper_1712_07973_amd as exx
     return exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R if s.bc != "periodic" else None)
+
+
+def kpsi_max_err(a: np.ndarray, b: np.ndarray) -> float:
+    """max_i max_r |a_i - b_i| / max_r |b_i|: element-wise, per orbital."""
+    N = a.shape[0]
+    num = np.abs(a - b).reshape(N, -1).max(1)
+    den = np.abs(b).reshape(N, -1).max(1)
+    return float(np.max(num / np.maximum(den, 1e-300)))
