@@ -4,17 +4,20 @@
 One step = one full evaluation of E_x and K psi (pair build, forward
 transforms, kernel multiply, inverse transforms, FP64 pair energies and
 K psi) for every orbital pair of one synthetic system, with inputs already
-resident in HBM.  Workload: isolated system, 64^3 grid zero-padded to 128^3,
-h = 0.4 bohr, 32 Loewdin-orthonormalised Gaussian orbitals with occupation 2,
-truncated Coulomb kernel with R = L, i.e. 528 pair Poisson solves per step.
+resident in HBM.  Default workload: isolated system, 128^3 grid zero-padded
+to 256^3, h = 0.4 bohr, 256 Loewdin-orthonormalised Gaussian orbitals (the
+last 16 fractionally occupied), truncated Coulomb kernel with R = L, i.e.
+32 896 pair Poisson solves per step.
 
 Prints one JSON line: pair-solves/s of the FP32 path (value), the plain FP64
-GPU path and the FP64 fused ablation beside it, per-pass device times from
-hipEvents recorded on the compute stream, the roofline of the dominant
-kernel, the accuracy against the plain FP64 path, and the FP64 CPU oracle's
-rate on a bounded sample.  The timed steps are eager calls; --graph times
-replays of one evaluation captured in a HIP graph instead (the eager rate is
-then reported beside it).
+GPU path beside it (on a labelled orbital subset when the full system would
+take long, with the FP32 path's accuracy against it on that subset), per-pass
+device times from hipEvents recorded on the compute stream, the roofline of
+the dominant kernel (its algorithmic bytes per launch over its measured
+launch time, against the HBM peak), and the FP64 CPU oracle's rate on a
+bounded sample at one core and at all cores.  The timed steps are eager
+calls; --graph times replays of one evaluation captured in a HIP graph
+instead (the eager rate is then reported beside it).
 """
 from __future__ import annotations
 
@@ -29,10 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, datasheet
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X vector FP32, datasheet (needs packed FP32)
-# The build keeps packed FP32 VALU ops off, so the attainable vector FP32 peak
-# is 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.
-FP32_UNPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X vector FP32, datasheet
 METRIC = "orbital-pair Poisson solves/s (E_x+Kψ) FP32-batched vs FP64, HBM GB/s"
 
 
@@ -62,6 +62,23 @@ def algorithmic_bytes(n: int, ncls: int, n_orb: int, n_slots: int, cplx: bool = 
         "pass_b": n_slots * 2 * x,
         "pass_c": n_slots * x + orb32 + kps,
     }
+
+
+def model_a_bytes(n: int, grid_classes: tuple, pairs: int, cplx: bool = False) -> dict:
+    """Algorithmic HBM bytes of the spectrum in the two-round-trip pipeline.
+
+    Pass A writes the spectrum half-way through the forward transform (x and
+    y done), pass B reads it, transforms z, multiplies by the kernel,
+    transforms back along z and writes it, pass C reads it.  Two real pairs
+    share one complex FP32 array, so a real pair costs 4 bytes per complex
+    point (a complex pair 8); the spectrum holds cx cy n^3 points (cx, cy the
+    x and y parity classes of the grid, the z axis pruned to the data's n
+    planes).  The orbital and K psi traffic, amortised over a pair tile, is
+    left out.  These are the bytes the roofline of each pass is quoted on.
+    """
+    cx, cy, _ = grid_classes
+    w = (8 if cplx else 4) * cx * cy * n ** 3 * pairs
+    return {"pass_a": w, "pass_b": 2 * w, "pass_c": w}
 
 
 def fft_flops(n: int, classes: tuple, n_slots: int) -> dict:
@@ -250,20 +267,38 @@ def autograd_times(grid, psi, occ, reps: int = 5) -> dict:
             "backward": "K psi recomputed, gradient -2 f h^3 K psi"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sysm, n_sample: int) -> dict:
-    """The FP64 oracle as it stands, timed on a subset of the orbitals."""
-    workers = min(16, os.cpu_count() or 1)
-    os.environ["EXX_ORACLE_WORKERS"] = str(workers)
+    """The FP64 oracle as it stands, timed on the first n_sample orbitals (every
+    pair among them, E_x and K psi) with scipy.fft on all host cores (at most
+    16) and on one core."""
     import oracle
+    from oracle import exx_oracle
     psi = sysm.psi[:n_sample].copy()
     occ = sysm.occ[:n_sample].copy()
     pairs = n_sample * (n_sample + 1) // 2
-    t0 = time.perf_counter()
-    oracle.exx(psi, occ, sysm.h, sysm.bc, R=sysm.R, symmetric=True)
-    dt = time.perf_counter() - t0
-    return {"value": pairs / dt, "unit": "pair-solves/s", "cores": workers, "kind": "oracle",
+    cores = min(16, os.cpu_count() or 1)
+    rate = {}
+    for workers in (cores, 1):
+        exx_oracle._WORKERS = workers
+        t0 = time.perf_counter()
+        oracle.exx(psi, occ, sysm.h, sysm.bc, R=sysm.R, symmetric=True)
+        rate[workers] = (pairs / (time.perf_counter() - t0), time.perf_counter() - t0)
+    return {"value": rate[cores][0], "unit": "pair-solves/s", "cores": cores, "kind": "oracle",
             "sample": f"all {pairs} pairs of the first {n_sample} of {sysm.n_orb} orbitals "
-                      f"(E_x and K psi), scipy.fft FP64 with workers={workers}, {dt:.1f} s"}
+                      f"(E_x and K psi), scipy.fft FP64: {rate[cores][1]:.1f} s with "
+                      f"workers={cores}, {rate[1][1]:.1f} s with workers=1",
+            "one_core": {"value": rate[1][0], "cores": 1}, "cpu_model": cpu_model()}
 
 
 def bench_batch(a, dev) -> int:
@@ -308,11 +343,16 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="free64_n32")
+    ap.add_argument("--workload", default="free128_n256")
     ap.add_argument("--baseline-steps", type=int, default=3)
     ap.add_argument("--no-baselines", action="store_true", help="skip the FP64 GPU paths")
+    ap.add_argument("--fp64-orbitals", type=int, default=0,
+                    help="orbitals of the FP64 legs (0: all when they take under ~2 s, else "
+                         "the first 32)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=12)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="orbitals of the oracle sample (0: 12 up to n = 64, 5 up to n = 96, "
+                         "else 3)")
     ap.add_argument("--slab-threads", type=int, default=0,
                     help="threads per slab workgroup of the y/z pass (0: plan default)")
     ap.add_argument("--tile", type=int, default=0, help="pair-tile edge (0: plan default)")
@@ -385,26 +425,31 @@ def main(argv=None) -> int:
     dom_ms, dom_launches = passes[dom]
     per_launch_ms = dom_ms / dom_launches
     launches_per_step = dom_launches / a.steps
-    alg = algorithmic_bytes(n, ncls, N, n_slots, cplx)
+    model = model_a_bytes(n, classes, pairs, cplx)
+    own = algorithmic_bytes(n, ncls, N, n_slots, cplx)
     flops = fft_flops(n, PASS_CLASSES[sysm.bc], n_slots)
-    bytes_per_launch = alg[dom] / launches_per_step
+    bytes_per_launch = model[dom] / launches_per_step
     achieved_gbs = bytes_per_launch / (per_launch_ms * 1e-3) / 1e9
+    own_per_launch = own[dom] / launches_per_step
+    own_gbs = own_per_launch / (per_launch_ms * 1e-3) / 1e9
     achieved_tflops = flops[dom] / launches_per_step / (per_launch_ms * 1e-3) / 1e12
-    hbm_frac = achieved_gbs / HBM_PEAK_GBS
-    alu_frac = achieved_tflops / FP32_UNPACKED_PEAK_TFLOPS
     traffic = measured_traffic(dom, a.workload)
-    hbm = {"achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(hbm_frac, 4), "algorithmic_bytes_per_launch": int(bytes_per_launch)}
-    alu = {"achieved": round(achieved_tflops, 2), "peak": round(FP32_UNPACKED_PEAK_TFLOPS, 1),
-           "unit": "TFLOP/s", "frac": round(alu_frac, 4),
-           "flops": "nominal 5 L log2 L per complex line transform",
-           "frac_of_packed_fp32_peak_157.3": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4)}
-    main = alu if alu_frac > hbm_frac else hbm
-    roofline = {"bound": "alu" if alu_frac > hbm_frac else "hbm", "kernel": dom,
-                "achieved": main["achieved"], "peak": main["peak"], "unit": main["unit"],
-                "frac": main["frac"], "traffic": traffic, "launch_ms": round(per_launch_ms, 4),
-                "hbm": hbm, "alu": alu}
-    whole_alg = sum(alg.values())
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved_gbs, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "launch_ms": round(per_launch_ms, 4),
+                "bytes_per_launch": int(bytes_per_launch),
+                "bytes_model": "two spectrum round trips, 4 B per real pair per complex point, "
+                               "cx cy n^3 points (z pruned)",
+                "own_minimum": {"bytes_per_launch": int(own_per_launch),
+                                "achieved": round(own_gbs, 1),
+                                "frac": round(own_gbs / HBM_PEAK_GBS, 4),
+                                "note": "the y,z spectrum never leaves the chip: pass B moves the "
+                                        "x-transformed slabs once each way"},
+                "fp32_flops": {"achieved": round(achieved_tflops, 2),
+                               "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": round(achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, 4),
+                               "flops": "nominal 5 L log2 L per complex line transform"}}
+    whole_model = sum(model.values())
 
     out = {
         "metric": METRIC,
@@ -426,39 +471,68 @@ def main(argv=None) -> int:
                    "slots": n_slots, "pairs_per_slot": 1 if cplx else 2,
                    "tuning": plan.tuning},
         "roofline": roofline,
-        "whole_step_algorithmic_GBs": round(whole_alg / (ms * 1e-3) / 1e9, 1),
+        "whole_step_model_GBs": round(whole_model / (ms * 1e-3) / 1e9, 1),
         "passes_ms_per_step": {k: round(v[0] / a.steps, 4) for k, v in passes.items()},
         "host_wall_ms_per_step": round(wall * 1e3 / a.steps, 4),
         "E_x": E32,
     }
+    if N <= 8:
+        out["us_per_call"] = round(ms * 1e3, 1)
 
     if not a.no_baselines:
-        for prec in ("fp64_plain", "fp64_fused"):
-            p64 = exx.Plan(grid, prec, n_orb_max=N, complex_orbitals=cplx)
-            p64.workspace(N)
-            k64 = torch.empty_like(psi)
+        # FP64 legs: every orbital when the plain path is quick, else a labelled
+        # subset (its rate per pair hardly depends on the orbital count: one pair
+        # per transform), with the FP32 path run on the same subset for the
+        # accuracy and a like-for-like rate
+        plain_pair_ms = 0.9 * (n / 128) ** 3 * (8 if sysm.bc == "free" else 2)
+        N64 = a.fp64_orbitals or (N if pair_count(N) * plain_pair_ms < 2000 else 32)
+        N64 = min(N64, N)
+        sub = {"orbitals": N64, "pairs": pair_count(N64),
+               "which": "all" if N64 == N else f"the first {N64} of {N}"}
+        psi_s, occ_s = psi[:N64].contiguous(), occ[:N64].contiguous()
+        k32s = torch.empty_like(psi_s)
+        e32s = torch.empty((), dtype=torch.float64, device=dev)
+        if N64 == N:
+            k32s.copy_(K32)
+            e32s.fill_(E32)
+            sub["fp32_value"] = round(value, 1)
+        else:
+            p32s = exx.Plan(grid, "fp32", n_orb_max=N64, complex_orbitals=cplx)
+            ms32s, _, _ = timed(p32s, psi_s, occ_s, k32s, e32s, a.baseline_steps, 1)
+            sub["fp32_value"] = round(pair_count(N64) / (ms32s * 1e-3), 1)
+            del p32s
+        precs = ["fp64_plain"] + (["fp64_fused"] if n <= 96 else [])
+        for prec in precs:
+            p64 = exx.Plan(grid, prec, n_orb_max=N64, complex_orbitals=cplx)
+            p64.workspace(N64)
+            k64 = torch.empty_like(psi_s)
             e64 = torch.empty((), dtype=torch.float64, device=dev)
-            ms64, _, _ = timed(p64, psi, occ, k64, e64, a.baseline_steps, 1, use_graph=a.graph)
-            out[prec] = {"value": round(pairs / (ms64 * 1e-3), 1), "ms_per_step": round(ms64, 3)}
+            ms64, _, _ = timed(p64, psi_s, occ_s, k64, e64, a.baseline_steps, 1, use_graph=a.graph)
+            out[prec] = {"value": round(pair_count(N64) / (ms64 * 1e-3), 1),
+                         "ms_per_step": round(ms64, 3), "subset": sub}
             if prec == "fp64_plain":
                 E64 = float(e64.item())
-                num = torch.linalg.vector_norm((K32 - k64).reshape(N, -1), dim=1)
-                den = torch.linalg.vector_norm(k64.reshape(N, -1), dim=1)
+                E32s = float(e32s.item())
+                d = (k32s - k64).reshape(N64, -1)
+                ref = k64.reshape(N64, -1)
+                num = torch.linalg.vector_norm(d, dim=1)
+                den = torch.linalg.vector_norm(ref, dim=1)
                 out["accuracy_vs_fp64_plain"] = {
-                    "dE_x_per_orbital_Ha": abs(E32 - E64) / N,
-                    "kpsi_max_rel_l2": float((num / den).max().item())}
-                out["speedup_vs_fp64_plain"] = round(value / out[prec]["value"], 2)
+                    "dE_x_per_orbital_Ha": abs(E32s - E64) / N64,
+                    "kpsi_max_rel_l2": float((num / den).max().item()),
+                    "kpsi_max_abs_rel": float((d.abs().amax(1) / ref.abs().amax(1)).max().item()),
+                    "orbitals": N64}
+                out["speedup_vs_fp64_plain"] = round(sub["fp32_value"] / out[prec]["value"], 2)
             del p64, k64
             torch.cuda.empty_cache()
-
-    if not a.no_baselines:
         copy_gbs = copy_bandwidth(dev)
         out["copy_bandwidth_GBs"] = round(copy_gbs, 1)
-        roofline["hbm"]["frac_of_copy_bandwidth"] = round(achieved_gbs / copy_gbs, 4)
+        roofline["frac_of_copy_bandwidth"] = round(achieved_gbs / copy_gbs, 4)
         out["autograd"] = autograd_times(grid, psi, occ)
 
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sysm, min(a.cpu_sample, N))
+        ns = a.cpu_sample or (12 if n <= 64 else (5 if n <= 96 else 3))
+        out["cpu_baseline"] = cpu_baseline(sysm, min(ns, N))
     print(json.dumps(out), flush=True)
     return 0
 

@@ -144,6 +144,19 @@ size_t slot_bytes(const exx_plan* p) {
 
 int max_tile(const exx_plan* p) { return pass_c_max_tile(p->precision, p->n, p->cplx); }
 
+// Default form of the y/z pass (FP32, 32 orbitals, ms of pass B per evaluation,
+// shared / wave): free n = 32 0.13 / 0.19, 64 1.32 / 1.30, 96 6.8 / 6.1,
+// 128 23.6 / 14.5; periodic n = 80 0.60 / 0.86, 128 2.78 / 2.58.  The wave-local
+// form wins from n = 48 on except on the periodic 80^3 grid.  FP64 plans keep
+// the workgroup-shared form by default (their wave-local form, n <= 80, is
+// selectable and tested but not the timed configuration).
+int default_slab_form(const exx_plan* p) {
+  if (!is_fp32(p) || !pass_b_wave_supported(p->precision, p->n)) return EXX_SLAB_SHARED;
+  if (p->n <= 32) return EXX_SLAB_SHARED;
+  if (p->ncls == 1 && p->cy == 1 && p->cz == 1 && p->n == 80) return EXX_SLAB_SHARED;
+  return EXX_SLAB_WAVE;
+}
+
 void default_tuning(exx_plan* p) {
   p->tuning.tile = max_tile(p);
   const size_t budget = (size_t)4 << 30;  // bytes of spectrum workspace per launch chunk
@@ -151,10 +164,7 @@ void default_tuning(exx_plan* p) {
   p->tuning.batch_slots = (int)std::max<size_t>(1, std::min<size_t>(budget / per, 1 << 20));
   p->tuning.slab_threads = (p->n == 64 && is_fp32(p)) ? 512 : 256;
   p->tuning.streams = 1;
-  p->tuning.slab_form = !is_plain(p) && pass_b_wave_supported(p->precision, p->n) &&
-                                is_fp32(p)
-                            ? EXX_SLAB_WAVE
-                            : EXX_SLAB_SHARED;
+  p->tuning.slab_form = default_slab_form(p);
 }
 
 int schedule_tile(const exx_plan* p) {
@@ -496,6 +506,40 @@ int validate_grid(const exx_grid* g, int precision) {
 
 }  // namespace
 
+int exx::compute_impl(exx_plan* p, const double* psi, const double* occ, int n_orb, int mode,
+                      unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
+                      size_t ws_bytes, void* stream, bool may_allocate) {
+  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
+  if (!psi || !occ) return fail(EXX_ERR_INVALID_ARG, "psi and occ are required");
+  if (n_orb <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb must be positive");
+  if (n_orb > p->n_orb_max) return fail(EXX_ERR_CAPACITY, "n_orb exceeds the plan's n_orb_max");
+  if (mode != EXX_MODE_ENERGY && mode != EXX_MODE_KPSI && mode != EXX_MODE_ENERGY_KPSI)
+    return fail(EXX_ERR_INVALID_ARG, "unknown mode");
+  if ((flags & ~EXX_FLAG_ACCUMULATE) != 0) return fail(EXX_ERR_INVALID_ARG, "unknown flags");
+  if ((mode & EXX_MODE_ENERGY) && !ex_out) return fail(EXX_ERR_INVALID_ARG, "ex_out is required for ENERGY modes");
+  if ((mode & EXX_MODE_KPSI) && !kpsi) return fail(EXX_ERR_INVALID_ARG, "kpsi is required for KPSI modes");
+  if (!aligned(psi, 16) || (kpsi && !aligned(kpsi, 16)) || !aligned(occ, 8) ||
+      (pair_e && !aligned(pair_e, 8)) || (ex_out && !aligned(ex_out, 8)))
+    return fail(EXX_ERR_ALIGNMENT, "psi/kpsi must be 16-byte aligned, scalars 8-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  EXX_HIP(hipStreamIsCapturing(st, &cap));
+  Schedule* s = nullptr;
+  // without allocation the schedule must already exist (exx_plan_prepare)
+  int rc = get_schedule(p, n_orb, &s, may_allocate && cap == hipStreamCaptureStatusNone);
+  if (rc) return rc;
+  WsLayout w = layout(p, *s);
+  if (!ws || ws_bytes < w.total)
+    return fail(EXX_ERR_WORKSPACE, "workspace smaller than exx_workspace_bytes(): need " + std::to_string(w.total));
+  if (!aligned(ws, 256)) return fail(EXX_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+  char* wsc = static_cast<char*>(ws);
+  // profiling events are created on first use: not in the allocation-free call
+  p->recording = (cap == hipStreamCaptureStatusNone) && may_allocate;
+  if (is_plain(p)) return run_plain(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+  if (is_fp32(p)) return run_fused<float>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+  return run_fused<double>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+}
+
 extern "C" {
 
 const char* exx_version(void) { return "exx 0.1 gfx950"; }
@@ -679,33 +723,8 @@ int exx_plan_set_tuning(exx_plan* p, const exx_tuning* t) {
 int exx_compute(exx_plan* p, const double* psi, const double* occ, int n_orb, int mode,
                 unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
                 size_t ws_bytes, void* stream) {
-  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
-  if (!psi || !occ) return fail(EXX_ERR_INVALID_ARG, "psi and occ are required");
-  if (n_orb <= 0) return fail(EXX_ERR_INVALID_ARG, "n_orb must be positive");
-  if (n_orb > p->n_orb_max) return fail(EXX_ERR_CAPACITY, "n_orb exceeds the plan's n_orb_max");
-  if (mode != EXX_MODE_ENERGY && mode != EXX_MODE_KPSI && mode != EXX_MODE_ENERGY_KPSI)
-    return fail(EXX_ERR_INVALID_ARG, "unknown mode");
-  if ((flags & ~EXX_FLAG_ACCUMULATE) != 0) return fail(EXX_ERR_INVALID_ARG, "unknown flags");
-  if ((mode & EXX_MODE_ENERGY) && !ex_out) return fail(EXX_ERR_INVALID_ARG, "ex_out is required for ENERGY modes");
-  if ((mode & EXX_MODE_KPSI) && !kpsi) return fail(EXX_ERR_INVALID_ARG, "kpsi is required for KPSI modes");
-  if (!aligned(psi, 16) || (kpsi && !aligned(kpsi, 16)) || !aligned(occ, 8) ||
-      (pair_e && !aligned(pair_e, 8)) || (ex_out && !aligned(ex_out, 8)))
-    return fail(EXX_ERR_ALIGNMENT, "psi/kpsi must be 16-byte aligned, scalars 8-byte aligned");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  EXX_HIP(hipStreamIsCapturing(st, &cap));
-  Schedule* s = nullptr;
-  int rc = get_schedule(p, n_orb, &s, cap == hipStreamCaptureStatusNone);
-  if (rc) return rc;
-  WsLayout w = layout(p, *s);
-  if (!ws || ws_bytes < w.total)
-    return fail(EXX_ERR_WORKSPACE, "workspace smaller than exx_workspace_bytes(): need " + std::to_string(w.total));
-  if (!aligned(ws, 256)) return fail(EXX_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
-  char* wsc = static_cast<char*>(ws);
-  p->recording = (cap == hipStreamCaptureStatusNone);
-  if (is_plain(p)) return run_plain(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
-  if (is_fp32(p)) return run_fused<float>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
-  return run_fused<double>(p, *s, w, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, wsc, st);
+  return exx::compute_impl(p, psi, occ, n_orb, mode, flags, ex_out, kpsi, pair_e, ws, ws_bytes,
+                           stream, true);
 }
 
 int exx_plan_enable_profiling(exx_plan* p, int enable) {

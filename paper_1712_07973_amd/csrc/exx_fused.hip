@@ -1406,9 +1406,19 @@ __global__ __launch_bounds__(NT) void k_pass_b3(cpx<T>* __restrict__ X, const cp
 // pairs (the first round, which holds every orbital once) store their row
 // sums, so K psi needs no clearing beforehand.
 // ---------------------------------------------------------------------------
-template <int N>
-constexpr int pass_c_tile() {  // K psi register budget: (tile + 1) * L1 FP64 values per thread
-  return N / 16 <= 4 ? 8 : 4;
+// Threads per owned row segment: above n = 64, where L1 = n / 16 is even, two
+// threads share each (row, t) segment of L1 points, each reducing half of them,
+// so that a pair tile of 8 orbitals fits the registers (its K psi sums are
+// (tile + 1) L1 / HP FP64 values per thread) and K psi is read and written half
+// as often as with a tile of 4.
+template <typename T, int N>
+constexpr int pass_c_halves() {
+  return (sizeof(T) == 4 && N > 64 && (N / 16) % 2 == 0) ? 2 : 1;
+}
+
+template <typename T, int N>
+constexpr int pass_c_tile() {  // K psi register budget: (tile + 1) * L1 / HP FP64 values per thread
+  return (N / 16 <= 4 || pass_c_halves<T, N>() == 2) ? 8 : 4;
 }
 
 // FP32 at n <= 32: ask for 3 waves per SIMD (168 registers); larger grids
@@ -1418,7 +1428,7 @@ constexpr int pass_c_min_waves() {
   return (sizeof(T) == 4 && N <= 32) ? 3 : 1;
 }
 
-template <typename T, int N, int NCLS, int ZB, int NT, int TM>
+template <typename T, int N, int NCLS, int ZB, int NT, int TM, int HP>
 __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const cpx<T>* __restrict__ X,
                                                const T* __restrict__ psi,
                                                const double* __restrict__ occ,
@@ -1438,7 +1448,9 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   constexpr int MAXS = TM * HB;               // slots per tile pair
   constexpr int NW = NT / 64;
   constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
-  static_assert(ZB * L2 == NT, "one point-owner item per thread");
+  constexpr int LP = L1 / HP;                 // points per thread
+  static_assert(ZB * L2 * HP == NT, "HP point-owner threads per (row, t)");
+  static_assert(L1 % HP == 0, "halves of equal size");
   static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
   // Spectrum rows of the current slot.  One buffer suffices: the store of
   // slot k+1 follows the second barrier of slot k, after every read of xs.
@@ -1451,14 +1463,21 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   __shared__ double fI[TM], fJ[TM];
   __shared__ double ered[MAXS][2][NW];
   __shared__ double etot[NW];
-  __shared__ T pJs[TM][L1 * NT];
+  // J-side orbital values at the owned points: LDS when one thread owns a
+  // segment, registers when it owns half of one
+  __shared__ T pJs[HP == 1 ? TM : 1][HP == 1 ? L1 * NT : 1];
+  T pJr[HP == 2 ? TM : 1][HP == 2 ? LP : 1];
 
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
   const int z0 = (blockIdx.x % (N / ZB)) * ZB;
   const TilePair tp = tiles[t0 + blockIdx.y];
   const size_t M3 = (size_t)N * N * N;
-  const int t_own = tid % L2, zi_own = tid / L2;
+  // owner of (row zi_own, t_own), points x = t_own + 16 k1 for k1 in [k0, k0 + LP)
+  // (threads of one half are contiguous, so K psi updates stay 128-byte runs)
+  const int h_own = tid / (ZB * L2), rt = tid % (ZB * L2);
+  const int t_own = rt % L2, zi_own = rt / L2;
+  const int k0 = h_own * LP;
   // offset of the owned row (swap_yz: spectrum (y, z) = grid (z, y))
   const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
   const int ns = tp.s1 - tp.s0;
@@ -1480,11 +1499,11 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     const int bb = ((sl.ia >= 0 ? sl.ja : sl.jb) - tp.J0) >> 1;
     smap[a][bb] = k;
   }
-  double accJ[TM][L1];
+  double accJ[TM][LP];
 #pragma unroll
   for (int b = 0; b < TM; ++b)
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) accJ[b][k1] = 0.0;
+    for (int k1 = 0; k1 < LP; ++k1) accJ[b][k1] = 0.0;
   double ew = 0.0;
 
   // spectrum rows of a slot: the block's rows are one contiguous z-block chunk
@@ -1506,7 +1525,13 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     if (b >= tp.nJ) continue;
     const T* po = psi + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * k1];
+    for (int k1 = 0; k1 < LP; ++k1) {
+      const T v = po[t_own + L2 * (k0 + k1)];
+      if constexpr (HP == 1)
+        pJs[b][k1 * NT + tid] = v;
+      else
+        pJr[b][k1] = v;
+    }
   }
   __syncthreads();
   if (ns > 0) fetch(0);
@@ -1514,14 +1539,14 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   int k = 0;  // running slot index (uniform)
 #pragma unroll 1
   for (int a = 0; a < tp.nI; ++a) {
-    double accI[L1];
-    T pI[L1];
+    double accI[LP];
+    T pI[LP];
     {
       const T* po = psi + (size_t)(tp.I0 + a) * M3 + row;
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) {
+      for (int k1 = 0; k1 < LP; ++k1) {
         accI[k1] = 0.0;
-        pI[k1] = po[t_own + L2 * k1];
+        pI[k1] = po[t_own + L2 * (k0 + k1)];
       }
     }
     const double fa = fI[a];
@@ -1555,21 +1580,25 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
         for (int t = 0; t < L2; ++t) xo[line * P + t + L2 * q1] = w[t];
       }
       __syncthreads();
-      // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b
-      cpx<T> V[L1];
+      // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b at the
+      // owned points (with two owners per segment both transform, each keeps half)
+      cpx<T> V[LP];
       {
         cpx<T> v[L1];
 #pragma unroll
         for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
         Dft<L1, 1, T>::run(v);
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) V[k1] = v[k1];
+        for (int k1 = 0; k1 < LP; ++k1) V[k1] = HP == 1 ? v[k1] : (h_own ? v[LP + k1] : v[k1]);
         if (NCLS == 2) {
 #pragma unroll
           for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
           Dft<L1, 1, T>::run(v);
 #pragma unroll
-          for (int k1 = 0; k1 < L1; ++k1) V[k1] = cadd(V[k1], cmulc(v[k1], md[t_own + L2 * k1]));
+          for (int k1 = 0; k1 < LP; ++k1) {
+            const cpx<T> w = HP == 1 ? v[k1] : (h_own ? v[LP + k1] : v[k1]);
+            V[k1] = cadd(V[k1], cmulc(w, md[t_own + L2 * (k0 + k1)]));
+          }
         }
       }
       // the two halves: J columns 2bb and 2bb + 1 (compile-time register indices)
@@ -1584,8 +1613,13 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
         const double fb = fJ[b];
         double e = 0.0;
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) {
-          const T pa = pI[k1], pb = pJs[b][k1 * NT + tid];
+        for (int k1 = 0; k1 < LP; ++k1) {
+          const T pa = pI[k1];
+          T pb;
+          if constexpr (HP == 1)
+            pb = pJs[b][k1 * NT + tid];
+          else
+            pb = pJr[b][k1];
           const double Vv = (double)(h ? V[k1].y : V[k1].x);
           e += (double)(pa * pb) * Vv;
           if (want_k) {
@@ -1618,14 +1652,14 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
         for (int b = 0; b < TM; ++b)
           if (b == a)
 #pragma unroll
-            for (int k1 = 0; k1 < L1; ++k1) accI[k1] += accJ[b][k1];
+            for (int k1 = 0; k1 < LP; ++k1) accI[k1] += accJ[b][k1];
       }
       if (want_k == 2 && tp.diag) {  // first write of this orbital row in the evaluation
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] = accI[k1];
+        for (int k1 = 0; k1 < LP; ++k1) ko[t_own + L2 * (k0 + k1)] = accI[k1];
       } else {
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += accI[k1];
+        for (int k1 = 0; k1 < LP; ++k1) ko[t_own + L2 * (k0 + k1)] += accI[k1];
       }
     }
   }
@@ -1636,7 +1670,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       if (b >= tp.nJ) continue;
       double* ko = kpsi + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
-      for (int k1 = 0; k1 < L1; ++k1) ko[t_own + L2 * k1] += accJ[b][k1];
+      for (int k1 = 0; k1 < LP; ++k1) ko[t_own + L2 * (k0 + k1)] += accJ[b][k1];
     }
   }
   if (!want_e) return;
@@ -2257,14 +2291,14 @@ int pass_c_max_tile(int precision, int n, bool cplx) {
   int t = 0;
   (void)dispatch_n(n, [&]<int N>() -> hipError_t {
     if (!cplx)
-      t = pass_c_tile<N>();
+      t = precision == EXX_PREC_FP64_FUSED ? pass_c_tile<double, N>() : pass_c_tile<float, N>();
     else if (precision == EXX_PREC_FP64_FUSED)
       t = pass_c_tile_cplx<double, N>();
     else
       t = pass_c_tile_cplx<float, N>();
     return hipSuccess;
   });
-  return t > 0 ? t : pass_c_tile<128>();
+  return t > 0 ? t : pass_c_tile<float, 128>();
 }
 
 template <typename T>
@@ -2278,8 +2312,9 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
       return hipErrorInvalidValue;
     } else {
       constexpr int ZB = XZ;
-      constexpr int NT = ZB * 16;
-      constexpr int TM = pass_c_tile<N>();
+      constexpr int HP = pass_c_halves<T, N>();
+      constexpr int NT = ZB * 16 * HP;
+      constexpr int TM = pass_c_tile<T, N>();
       dim3 grid(N * (N / ZB), ntiles);
       auto* Xc = static_cast<const cpx<T>*>(X);
       auto* tw = static_cast<const cpx<T>*>(tb.tw);
@@ -2290,22 +2325,22 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
         auto* pc = reinterpret_cast<const cpx<T>*>(psi);
         auto* kc = reinterpret_cast<cpx<double>*>(kpsi);
         if (L.ncls == 2)
-          hipLaunchKernelGGL((k_pass_c_cplx<T, N, 2, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
+          hipLaunchKernelGGL((k_pass_c_cplx<T, N, 2, ZB, ZB * 16, TMC>), grid, dim3(ZB * 16), 0, L.stream, Xc,
                              pc, occ, slots, tiles, t0, slot_base, kc, e_slot, k_mode,
                              want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         else
-          hipLaunchKernelGGL((k_pass_c_cplx<T, N, 1, ZB, NT, TMC>), grid, dim3(NT), 0, L.stream, Xc,
+          hipLaunchKernelGGL((k_pass_c_cplx<T, N, 1, ZB, ZB * 16, TMC>), grid, dim3(ZB * 16), 0, L.stream, Xc,
                              pc, occ, slots, tiles, t0, slot_base, kc, e_slot, k_mode,
                              want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         return hipGetLastError();
       }
       if (tmax > TM) return hipErrorInvalidValue;
       if (L.ncls == 2)
-        hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
+        hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
                            want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
       else
-        hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM>), grid, dim3(NT), 0, L.stream, Xc, psi,
+        hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc, psi,
                            occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
                            want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
       return hipGetLastError();

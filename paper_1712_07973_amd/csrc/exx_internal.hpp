@@ -107,6 +107,13 @@ hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, cons
 
 bool fused_supported(int precision, int n);
 
+// Body of exx_compute.  may_allocate = false: no device allocation and no event
+// creation (the schedule for n_orb must already be prepared, profiling events
+// are not recorded); the workspace is whatever the caller passes.
+int compute_impl(exx_plan* p, const double* psi, const double* occ, int n_orb, int mode,
+                 unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
+                 size_t ws_bytes, void* stream, bool may_allocate);
+
 // Record msg (or the HIP error) as this thread's exx_last_error() and return
 // the code (EXX_ERR_HIP for the second).
 int record_error(int code, const std::string& msg);
