@@ -93,7 +93,10 @@ enum exx_kernel { EXX_KERNEL_COULOMB = 0, EXX_KERNEL_SCREENED = 1, EXX_KERNEL_IS
 enum exx_precision { EXX_PREC_FP32 = 0, EXX_PREC_FP64_PLAIN = 1, EXX_PREC_FP64_FUSED = 2 };
 
 /* What to compute.  ENERGY alone uses Parseval's identity (one forward
- * transform per pair) unless pair energies are requested. */
+ * transform per pair) unless pair energies are requested; that route folds
+ * sqrt(f_i f_j) into the co-densities and so needs f_i >= 0 (a negative f_i
+ * counts as 0 there): for signed occupations request pair_e, which takes the
+ * route through the potentials (the Python binding does so by itself). */
 enum exx_mode { EXX_MODE_ENERGY = 1, EXX_MODE_KPSI = 2, EXX_MODE_ENERGY_KPSI = 3 };
 
 /* Flags of exx_compute / exx_batch_compute. */

@@ -178,6 +178,11 @@ class Plan:
             ex_out = torch.empty((), dtype=torch.float64, device=self.device)
         if m & L.MODE_KPSI and kpsi is None:
             kpsi = torch.empty_like(psi)
+        keep_pe = pair_e is not None
+        if m == L.MODE_ENERGY and pair_e is None and bool((occ < 0).any()):
+            # the energy-only route folds sqrt(f_i f_j) into the co-densities, which
+            # needs f >= 0: with a negative occupation take the pair-energy route
+            pair_e = torch.empty((N, N), dtype=torch.float64, device=self.device)
         if kpsi is not None:
             _check_tensor("kpsi", kpsi, (N, n, n, n), self.device, self.dtype)
         if pair_e is not None:
@@ -189,7 +194,7 @@ class Plan:
                                      _ptr(ex_out), _ptr(kpsi), _ptr(pair_e), ws.data_ptr(),
                                      ws.numel(), _stream_ptr(self.device))
         L.check(rc, "exx_compute")
-        return ex_out, kpsi, pair_e
+        return ex_out, kpsi, (pair_e if keep_pe else None)
 
     def autotune(self, psi: torch.Tensor, occ: torch.Tensor, cache_path: str | None = None,
                  budget_ms: int = 0) -> dict:

@@ -10,7 +10,8 @@
   diagonal slot in the schedule;
 * an orbital with zero occupation (it still receives K psi, contributes none);
 * batches of real-orbital systems against the oracle, not only against
-  single-system calls.
+  single-system calls;
+* a negative occupation in the energy-only mode (signed weights kept).
 """
 import numpy as np
 import pytest
@@ -153,3 +154,21 @@ def test_real_batch_matches_oracle(precision, use_graph):
         torch.cuda.synchronize()
         for s, r, (ex, kp) in zip(systems, refs, outs):
             _check(s, r, ex.item(), kp.cpu().numpy(), None, precision, s.n_orb)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_fused"])
+def test_negative_occupation_energy_only(precision):
+    # the energy-only (Parseval) route needs f >= 0; the binding takes the
+    # pair-energy route for signed occupations, so E_x keeps the signs
+    say(f"[f<0] {precision}")
+    s = small_system("free", 32, 4, seed=77)
+    occ_np = np.array([2.0, -0.4, 1.1, 0.7])
+    ref = oracle.exx(s.psi, occ_np, s.h, "free", symmetric=True, want_kpsi=False)
+    psi = torch.from_numpy(s.psi).to(DEV)
+    occ = torch.from_numpy(occ_np).to(DEV)
+    plan = exx.Plan(grid_of(s), precision, n_orb_max=4)
+    ex, _, pe = plan.compute(psi, occ, "energy")
+    torch.cuda.synchronize()
+    assert pe is None
+    tol = 1e-6 * 4 if precision == "fp32" else TOL_FP64_E * abs(ref["E"])
+    assert abs(ex.item() - ref["E"]) <= tol

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from gpu_common import (TOL_FP32_E_PER_ORB, TOL_FP32_K, TOL_FP64_E, TOL_FP64_K, grid_of,
-                        kpsi_rel_err, oracle_result, say)
+                        kpsi_max_err, kpsi_rel_err, oracle_result, say)
 
 pytestmark = pytest.mark.gpu
 
@@ -167,24 +167,29 @@ def test_kpsi_output_is_overwritten(bc, precision, kmax):
 
 
 def test_fp32_odd_slot_chunks_above_n64():
-    # Above n = 64 a pass A block takes two consecutive slots; launch chunks of
-    # 5 slots from tiles of 3 (9 pairs, 5 packed slots per off-diagonal tile
-    # pair) leave a one-slot last block in every launch.
-    bc, n, N, seed = "free", 80, 7, 45
+    # Above n = 64 a pass A block takes two consecutive slots.  Five orbitals in
+    # tiles of 3 (sizes 3 and 2) give two launch chunks of 5 slots each (the
+    # schedule is checked on the CPU in test_schedule_cpu.py): the first holds the
+    # large diagonal tile pair, the second the small diagonal one and the
+    # off-diagonal pair with its ragged 2-orbital edge, so both launches end in a
+    # one-slot pass A block, one of them on an off-diagonal tile pair.
+    bc, n, N, seed = "free", 80, 5, 45
     say(f"[parity chunks] fp32 {bc} n={n} N={N} seed={seed} tile=3 batch_slots=5")
     s, ref = oracle_result(bc, n, N, seed, 0)
     dev = torch.device("cuda", 0)
     plan = exx.Plan(grid_of(s), "fp32", n_orb_max=N)
     plan.set_tuning(tile=3, batch_slots=5)
     assert plan.tuning["tile"] == 3
+    assert plan.schedule_info(N) == (15, 10)
     plan.enable_profiling(True)
     plan.read_profile()
     pe = torch.empty((N, N), dtype=torch.float64, device=dev)
     ex, kp, pe = plan.compute(torch.from_numpy(s.psi).to(dev), torch.from_numpy(s.occ).to(dev),
                               "energy_kpsi", pair_e=pe)
     torch.cuda.synchronize()
-    assert plan.read_profile()["pass_a"][1] > 1
+    assert plan.read_profile()["pass_a"][1] == 2  # one launch per chunk
     assert abs(ex.item() - ref["E"]) / N < TOL_FP32_E_PER_ORB
     assert kpsi_rel_err(kp.cpu().numpy(), ref["kpsi"]) < TOL_FP32_K
+    assert kpsi_max_err(kp.cpu().numpy(), ref["kpsi"]) < TOL_FP32_K
     P = pe.cpu().numpy()
     assert np.max(np.abs(P - ref["pair_e"])) <= 1e-6 * np.max(np.abs(ref["pair_e"]))

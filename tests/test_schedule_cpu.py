@@ -139,3 +139,17 @@ def test_single_pair_tiled_schedule_invariants(probe, N, T, cap):
         assert s1 - s0 <= max(cap, T * T)
         t_prev, s_prev = t1, s1
     assert s_prev == len(r["S"]) and t_prev == len(r["T"])
+
+
+def test_odd_chunks_with_an_off_diagonal_tile_pair(probe):
+    # five orbitals in tiles of 3 (sizes 3 and 2), at most 5 slots per launch
+    # (raised to one full tile pair, 6): chunks of 5 and 5 slots, the second
+    # holding the small diagonal tile pair and the ragged off-diagonal one; the
+    # GPU test of odd pass A chunks above n = 64 relies on exactly this
+    head, r = run(probe, 5, 3, 5)
+    sizes = [s1 - s0 for (t0, t1, s0, s1, g0, g1) in r["C"]]
+    assert sizes == [5, 5]
+    t0, t1 = r["C"][1][:2]
+    assert any(r["T"][t][6] == 0 for t in range(t0, t1))  # an off-diagonal tile pair
+    off = [t for t in range(t0, t1) if r["T"][t][6] == 0][0]
+    assert r["T"][off][1] - r["T"][off][0] == 3  # three rows of one column pair
