@@ -167,6 +167,25 @@ int exx_compute(exx_plan* plan, const double* psi, const double* occ, int n_orb,
                 unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
                 size_t ws_bytes, void* stream);
 
+/* exx_compute without any allocation, for callers that cannot allocate (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and stream ordering as exx_compute, but
+ * the workspace is the library's own static device array of
+ * EXX_NOALLOC_SCRATCH_BYTES per GPU (held from the library's first use of that
+ * GPU to the end of the process), and nothing is allocated: the plan's
+ * schedule for n_orb must already exist (exx_plan_prepare, or an earlier
+ * exx_compute), else EXX_ERR_NOT_PREPARED; profiling events are not recorded.
+ * The current device must be the plan's.  A problem whose workspace
+ * (exx_workspace_bytes) exceeds the maximum gives EXX_ERR_WORKSPACE with the
+ * sizes in exx_last_error(); lower the plan's batch_slots (exx_plan_set_tuning,
+ * then exx_plan_prepare) to fit.  Every call on a GPU uses the same array:
+ * calls that overlap on one GPU (other streams, other threads) race, and the
+ * array keeps the last call's contents (no part of it needs clearing). */
+#define EXX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int exx_compute_noalloc(exx_plan* plan, const double* psi, const double* occ, int n_orb,
+                        int mode, unsigned flags, double* ex_out, double* kpsi, double* pair_e,
+                        void* stream);
+
 /* Tuning knobs of a plan (pair-tile edge, slots per launch, slab workgroup
  * size, pass streams).  Returned by exx_autotune and settable explicitly;
  * a field left 0 keeps the plan's value.  Every setting gives the same

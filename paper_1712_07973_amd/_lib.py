@@ -62,6 +62,8 @@ SIGNATURES = {
     "exx_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "exx_compute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_uint,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "exx_compute_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
+                                      C.c_uint, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "exx_plan_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(ExxTuning)]),
     "exx_plan_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(ExxTuning)]),
     "exx_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,

@@ -196,6 +196,33 @@ class Plan:
         L.check(rc, "exx_compute")
         return ex_out, kpsi, (pair_e if keep_pe else None)
 
+    def compute_noalloc(self, psi: torch.Tensor, occ: torch.Tensor, mode: str = "energy_kpsi",
+                        kpsi: torch.Tensor | None = None, pair_e: torch.Tensor | None = None,
+                        ex_out: torch.Tensor | None = None, accumulate: bool = False):
+        """exx_compute_noalloc: the library's static per-GPU workspace instead of a
+        caller's; every output tensor must be passed in (nothing is allocated) and
+        the schedule for this orbital count must be prepared."""
+        n = self.grid.n
+        N = int(psi.shape[0])
+        _check_tensor("psi", psi, (N, n, n, n), self.device, self.dtype)
+        _check_tensor("occ", occ, (N,), self.device)
+        m = MODES[mode]
+        if m & L.MODE_ENERGY and ex_out is None:
+            raise ValueError("ex_out is required for energy modes (nothing is allocated)")
+        if m & L.MODE_KPSI and kpsi is None:
+            raise ValueError("kpsi is required for K psi modes (nothing is allocated)")
+        if kpsi is not None:
+            _check_tensor("kpsi", kpsi, (N, n, n, n), self.device, self.dtype)
+        if pair_e is not None:
+            _check_tensor("pair_e", pair_e, (N, N), self.device)
+        flags = L.FLAG_ACCUMULATE if accumulate else 0
+        with torch.cuda.device(self.device):
+            rc = L.lib().exx_compute_noalloc(self._h, psi.data_ptr(), occ.data_ptr(), N, m, flags,
+                                             _ptr(ex_out), _ptr(kpsi), _ptr(pair_e),
+                                             _stream_ptr(self.device))
+        L.check(rc, "exx_compute_noalloc")
+        return ex_out, kpsi, pair_e
+
     def autotune(self, psi: torch.Tensor, occ: torch.Tensor, cache_path: str | None = None,
                  budget_ms: int = 0) -> dict:
         N = int(psi.shape[0])

@@ -23,7 +23,7 @@ LIB = os.path.join(PKG, "libexx.so")
 ARCH = os.environ.get("EXX_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["exx_fused.hip", "exx_plain.hip", "exx_api.cpp", "exx_batch.cpp", "exx_schedule.cpp",
-           "exx_isf.cpp"]
+           "exx_isf.cpp", "exx_static.hip"]
 
 COMMON = [
     "-std=c++20", "-O3", "-fPIC", f"--offload-arch={ARCH}",
