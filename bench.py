@@ -22,6 +22,7 @@ instead (the eager rate is then reported beside it).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -204,7 +205,9 @@ def workload_text(sysm, pairs: int) -> str:
     """What the single-system workload is, with its sizes."""
     n, h, N = sysm.n, sysm.h, sysm.n_orb
     L = n * h
-    geom = {"free": f"free-BC {n}^3 grid padded to {2 * n}^3, h={h} bohr, R=L={L:g} bohr",
+    rtxt = f"R=L={L:g} bohr" if abs(sysm.R - L) < 1e-12 * L else \
+        f"R=sqrt(3)L={sysm.R:g} bohr (box diagonal; aliases on the padded grid)"
+    geom = {"free": f"free-BC {n}^3 grid padded to {2 * n}^3, h={h} bohr, {rtxt}",
             "surface": f"surface (periodic x, y; isolated z) {n}^3 grid padded to {n}x{n}x{2 * n}, "
                        f"h={h} bohr, R=L={L:g} bohr",
             "wire": f"wire (isolated x, y; periodic z) {n}^3 grid padded to {2 * n}x{2 * n}x{n}, "
@@ -302,7 +305,8 @@ def cpu_baseline(sysm, n_sample: int) -> dict:
 
 
 def bench_batch(a, dev) -> int:
-    """Sixteen uneven isolated systems in one captured HIP graph (FP32 path)."""
+    """Sixteen uneven isolated systems in one captured HIP graph (FP32 path),
+    tuned per grid class by exx_batch_autotune before timing."""
     import torch
 
     import paper_1712_07973_amd as exx
@@ -313,6 +317,9 @@ def bench_batch(a, dev) -> int:
     occs = [torch.from_numpy(s.occ).to(dev) for s in systems]
     pairs = sum(pair_count(s.n_orb) for s in systems)
     b = exx.Batch(grids, [s.n_orb for s in systems], "fp32", use_graph=True)
+    t0 = time.perf_counter()
+    tunings = b.autotune(psis, occs, budget_ms=a.batch_tune_ms) if a.batch_tune_ms > 0 else b.tunings()
+    tune_s = time.perf_counter() - t0
     outs = None
     for _ in range(max(1, a.warmup)):
         outs = b.compute(psis, occs, outputs=outs)
@@ -326,14 +333,56 @@ def bench_batch(a, dev) -> int:
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / a.steps
+    model = sum(sum(model_a_bytes(s.n, CLASSES[s.bc], pair_count(s.n_orb)).values()) for s in systems)
+    gbs = model / (ms * 1e-3) / 1e9
     out = {"metric": METRIC, "value": round(pairs / (ms * 1e-3), 1), "unit": "pair-solves/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": "16 isolated systems, n in {48..112} padded to 2n, N in [16,96], "
-                                  "one captured HIP graph per evaluation",
-                      "pairs": pairs, "systems": [[s.n, s.n_orb] for s in systems]},
+                                  "one captured HIP graph per evaluation, tuned per grid class",
+                      "pairs": pairs, "systems": [[s.n, s.n_orb] for s in systems],
+                      "tunings": tunings, "autotune_s": round(tune_s, 1)},
+           "roofline": {"bound": "hbm", "kernel": "whole evaluation (every pass of every system)",
+                        "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_launch": int(model),
+                        "bytes_model": "two spectrum round trips, 4 B per real pair per complex "
+                                       "point, cx cy n^3 points (z pruned)"},
            "E_x": [float(o[0].item()) for o in outs]}
+    del b
+    torch.cuda.empty_cache()
+    if not a.no_baselines:
+        # FP64 leg: the plain path on the systems of n <= 64 (a labelled subset),
+        # with the FP32 batch of the same systems beside it
+        sub = [k for k, s in enumerate(systems) if s.n <= 64]
+        sp = sum(pair_count(systems[k].n_orb) for k in sub)
+        rates = {}
+        for prec in ("fp32", "fp64_plain"):
+            bs = exx.Batch([grids[k] for k in sub], [systems[k].n_orb for k in sub], prec,
+                           use_graph=True)
+            o = bs.compute([psis[k] for k in sub], [occs[k] for k in sub])
+            torch.cuda.synchronize()
+            e0.record(stream)
+            reps = 3 if prec == "fp32" else 1
+            for _ in range(reps):
+                bs.compute([psis[k] for k in sub], [occs[k] for k in sub], outputs=o)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rates[prec] = (sp / (e0.elapsed_time(e1) / reps * 1e-3), [float(x[0].item()) for x in o])
+            del bs
+            torch.cuda.empty_cache()
+        out["fp64_plain"] = {"value": round(rates["fp64_plain"][0], 1),
+                             "subset": {"systems": [[systems[k].n, systems[k].n_orb] for k in sub],
+                                        "pairs": sp, "fp32_value": round(rates["fp32"][0], 1)}}
+        out["accuracy_vs_fp64_plain"] = {"dE_x_per_orbital_Ha_max": max(
+            abs(e32 - e64) / systems[k].n_orb
+            for k, e32, e64 in zip(sub, rates["fp32"][1], rates["fp64_plain"][1]))}
+        out["speedup_vs_fp64_plain"] = round(rates["fp32"][0] / rates["fp64_plain"][0], 2)
+    if not a.no_cpu_baseline:
+        big = max(range(len(systems)), key=lambda k: systems[k].n)
+        out["cpu_baseline"] = cpu_baseline(systems[big], a.cpu_sample or 3)
+        out["cpu_baseline"]["sample"] += f" (system {big}: n = {systems[big].n})"
     print(json.dumps(out), flush=True)
     return 0
 
@@ -365,6 +414,11 @@ def main(argv=None) -> int:
     ap.add_argument("--graph", action="store_true",
                     help="time replays of one evaluation captured in a HIP graph (measured within "
                          "0.5 %% of eager calls at the default workload)")
+    ap.add_argument("--batch-tune-ms", type=int, default=20000,
+                    help="autotuning budget of the batch workload (0: plan defaults)")
+    ap.add_argument("--radius", default="box", choices=["box", "diagonal"],
+                    help="free-BC truncation radius: box (R = L = n h, the default) or diagonal "
+                         "(R = sqrt(3) L; the 2n-padded grid then aliases periodic images)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates memory counters)")
     a = ap.parse_args(argv)
@@ -397,6 +451,11 @@ def main(argv=None) -> int:
         return bench_batch(a, dev)
     sysm = system(a.workload)
     N, n = sysm.n_orb, sysm.n
+    if a.radius == "diagonal":
+        if sysm.bc != "free":
+            print("--radius diagonal applies to free-BC workloads only", file=sys.stderr)
+            return 2
+        sysm = dataclasses.replace(sysm, R=math.sqrt(3.0) * n * sysm.h)
     pairs = pair_count(N)
     classes = CLASSES[sysm.bc]
     ncls = classes[0]
@@ -478,6 +537,16 @@ def main(argv=None) -> int:
     }
     if N <= 8:
         out["us_per_call"] = round(ms * 1e3, 1)
+    if a.radius == "diagonal":
+        gbox = exx.Grid(n=n, h=sysm.h, bc=sysm.bc, R=n * sysm.h)
+        pbox = exx.Plan(gbox, "fp32", n_orb_max=N, complex_orbitals=cplx)
+        ebox, _, _ = pbox.compute(psi, occ, "energy")
+        out["radius_reading"] = {
+            "R_bohr": sysm.R, "E_x": E32, "E_x_with_R_eq_L": float(ebox.item()),
+            "relative_difference": abs(E32 - float(ebox.item())) / abs(float(ebox.item())),
+            "note": "R = box diagonal read literally; on a 2n-padded grid the truncated kernel "
+                    "then reaches periodic images, so R = L is the default"}
+        del pbox
 
     if not a.no_baselines:
         # FP64 legs: every orbital when the plain path is quick, else a labelled

@@ -167,6 +167,25 @@ int exx_compute(exx_plan* plan, const double* psi, const double* occ, int n_orb,
                 unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
                 size_t ws_bytes, void* stream);
 
+/* Gradient of E_x for reverse-mode differentiation (Eq. 3 and Eq. 5: E_x is a
+ * quartic in the orbitals and a quadratic in the occupations).
+ *   gbar     device FP64 scalar: the derivative of the caller's loss with
+ *            respect to E_x (read on the device, so no host sync is needed);
+ *   grad_psi device FP64 like psi, overwritten with
+ *            gbar dE_x/dpsi_k(r) = -2 gbar f_k h^3 (K psi)_k(r); for a complex
+ *            plan, the derivative with respect to Re psi plus i times the one
+ *            with respect to Im psi;
+ *   grad_occ device FP64 [n_orb] or NULL: gbar dE_x/df_k = -gbar sum_j f_j e_kj;
+ *   pair_e   device FP64 [n_orb][n_orb], required with grad_occ (it receives the
+ *            pair energies e_kj), ignored without;
+ * psi, occ, n_orb, ws, ws_bytes and stream as exx_compute (the evaluation is
+ * exx_compute in KPSI mode, recomputing every pair potential; signed
+ * occupations are allowed).  Errors as exx_compute, plus EXX_ERR_INVALID_ARG
+ * for a missing gbar or grad_psi, or grad_occ without pair_e. */
+int exx_gradient(exx_plan* plan, const double* psi, const double* occ, int n_orb,
+                 const double* gbar, double* grad_psi, double* grad_occ, double* pair_e, void* ws,
+                 size_t ws_bytes, void* stream);
+
 /* exx_compute without any allocation, for callers that cannot allocate (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  Same arguments, results and stream ordering as exx_compute, but
@@ -252,6 +271,18 @@ void exx_batch_destroy(exx_batch* batch);
 int exx_batch_workspace_bytes(const exx_batch* batch, size_t* bytes);
 int exx_batch_compute(exx_batch* batch, const exx_system* systems, int mode, unsigned flags,
                       void* ws, size_t ws_bytes, void* stream);
+
+/* Autotunes a batch: its systems are grouped by grid (same kernels and kernel
+ * table); exx_autotune runs on each group's member with the most orbitals, on
+ * that system's psi, occ and (as scratch) K psi buffers and its share of ws,
+ * with budget_ms split over the groups, and the winning tuning is applied to
+ * every member of the group whose share of the workspace holds it.  The
+ * workspace size does not change.  Synchronises the stream; a graph captured
+ * earlier is captured again on the next exx_batch_compute. */
+int exx_batch_autotune(exx_batch* batch, const exx_system* systems, void* ws, size_t ws_bytes,
+                       void* stream, int budget_ms, const char* cache_path);
+/* The tuning of system `system`'s plan (0 <= system < n_systems). */
+int exx_batch_get_tuning(const exx_batch* batch, int system, exx_tuning* out);
 
 /* ---- profiling ----------------------------------------------------------- */
 /* Per-pass device time measured with hipEvents recorded on the compute stream

@@ -62,6 +62,9 @@ SIGNATURES = {
     "exx_workspace_bytes": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_size_t)]),
     "exx_compute": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_uint,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "exx_gradient": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                               C.c_void_p]),
     "exx_compute_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_int,
                                       C.c_uint, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "exx_plan_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(ExxTuning)]),
@@ -74,6 +77,9 @@ SIGNATURES = {
     "exx_batch_workspace_bytes": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "exx_batch_compute": (C.c_int, [C.c_void_p, C.POINTER(ExxSystem), C.c_int, C.c_uint, C.c_void_p,
                                     C.c_size_t, C.c_void_p]),
+    "exx_batch_autotune": (C.c_int, [C.c_void_p, C.POINTER(ExxSystem), C.c_void_p, C.c_size_t,
+                                     C.c_void_p, C.c_int, C.c_char_p]),
+    "exx_batch_get_tuning": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(ExxTuning)]),
     "exx_error_string": (C.c_char_p, [C.c_int]),
     "exx_last_error": (C.c_char_p, []),
     "exx_plan_schedule_info": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_longlong),

@@ -196,6 +196,25 @@ class Plan:
         L.check(rc, "exx_compute")
         return ex_out, kpsi, (pair_e if keep_pe else None)
 
+    def gradient(self, psi: torch.Tensor, occ: torch.Tensor, gbar: torch.Tensor,
+                 want_occ: bool = False, workspace: torch.Tensor | None = None):
+        """exx_gradient: (gbar dE_x/dpsi, gbar dE_x/df or None), gbar a device scalar."""
+        n = self.grid.n
+        N = int(psi.shape[0])
+        _check_tensor("psi", psi, (N, n, n, n), self.device, self.dtype)
+        _check_tensor("occ", occ, (N,), self.device)
+        _check_tensor("gbar", gbar, (), self.device)
+        grad_psi = torch.empty_like(psi)
+        grad_occ = torch.empty((N,), dtype=torch.float64, device=self.device) if want_occ else None
+        pe = torch.empty((N, N), dtype=torch.float64, device=self.device) if want_occ else None
+        ws = workspace if workspace is not None else self.workspace(N)
+        with torch.cuda.device(self.device):
+            rc = L.lib().exx_gradient(self._h, psi.data_ptr(), occ.data_ptr(), N, gbar.data_ptr(),
+                                      grad_psi.data_ptr(), _ptr(grad_occ), _ptr(pe), ws.data_ptr(),
+                                      ws.numel(), _stream_ptr(self.device))
+        L.check(rc, "exx_gradient")
+        return grad_psi, grad_occ
+
     def compute_noalloc(self, psi: torch.Tensor, occ: torch.Tensor, mode: str = "energy_kpsi",
                         kpsi: torch.Tensor | None = None, pair_e: torch.Tensor | None = None,
                         ex_out: torch.Tensor | None = None, accumulate: bool = False):

@@ -1,8 +1,9 @@
 """E_x as a differentiable function of the orbitals (and occupations).
 
 Forward: E_x alone (exx_compute in ENERGY mode, no pair potential stored).
-Backward: recomputes every pair potential (exx_compute in KPSI mode) and
-returns the exact gradient of the grid function,
+Backward: exx_gradient, which recomputes every pair potential (KPSI mode) and
+returns, scaled on the device by the upstream derivative, the exact gradient
+of the grid function,
 
     dE_x / dpsi_k(r) = -2 f_k h^3 (K psi)_k(r),
     dE_x / df_k      = -sum_j f_j e_kj,
@@ -39,16 +40,12 @@ class ExchangeEnergy(torch.autograd.Function):
         grid, precision = ctx.grid, ctx.precision
         plan = get_plan(grid, precision, psi.shape[0], psi.device, psi.is_complex())
         need_psi, need_occ = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        gpsi = gocc = None
-        N = psi.shape[0]
-        pe = torch.empty((N, N), dtype=torch.float64, device=psi.device) if need_occ else None
-        if need_psi or need_occ:
-            _, kpsi, pe = plan.compute(psi, occ, "kpsi", pair_e=pe)
-            if need_psi:
-                gpsi = kpsi.mul_((-2.0 * grid.h3) * occ.view(-1, 1, 1, 1)).mul_(g)
-            if need_occ:
-                gocc = -(pe @ occ) * g
-        return gpsi, gocc, None, None
+        if not (need_psi or need_occ):
+            return None, None, None, None
+        gbar = g.detach().to(device=psi.device, dtype=torch.float64).contiguous()
+        # the library recomputes K psi and scales it (exx_gradient)
+        gpsi, gocc = plan.gradient(psi, occ, gbar, want_occ=need_occ)
+        return (gpsi if need_psi else None), gocc, None, None
 
 
 def exchange_energy(psi: torch.Tensor, occ: torch.Tensor, grid: Grid,

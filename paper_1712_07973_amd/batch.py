@@ -50,6 +50,44 @@ class Batch:
                 pass
             self._h = None
 
+    def _systems(self, psis, occs, outputs, m):
+        S = len(self.grids)
+        sysarr = (L.ExxSystem * S)()
+        for s in range(S):
+            n = self.grids[s].n
+            _check_tensor("psi", psis[s], (self.n_orb[s], n, n, n), self.device, self.dtype)
+            _check_tensor("occ", occs[s], (self.n_orb[s],), self.device)
+            ex, kp = outputs[s]
+            sysarr[s].psi = psis[s].data_ptr()
+            sysarr[s].occ = occs[s].data_ptr()
+            sysarr[s].ex_out = ex.data_ptr() if (m & L.MODE_ENERGY) else None
+            sysarr[s].kpsi = kp.data_ptr() if kp is not None else None
+            sysarr[s].pair_e = None
+        return sysarr
+
+    def autotune(self, psis, occs, budget_ms: int = 20000, cache_path: str | None = None) -> list:
+        """exx_batch_autotune: picks the tuning per grid class on the given inputs
+        (K psi buffers of the right shape serve as scratch); returns the tunings."""
+        outputs = [(torch.empty((), dtype=torch.float64, device=self.device), torch.empty_like(p))
+                   for p in psis]
+        sysarr = self._systems(psis, occs, outputs, L.MODE_ENERGY_KPSI)
+        with torch.cuda.device(self.device):
+            rc = L.lib().exx_batch_autotune(self._h, sysarr, self.ws.data_ptr(), self.ws.numel(),
+                                            _stream_ptr(self.device), int(budget_ms),
+                                            cache_path.encode() if cache_path else None)
+        L.check(rc, "exx_batch_autotune")
+        return self.tunings()
+
+    def tunings(self) -> list:
+        """The tuning of every system's plan."""
+        out = []
+        for s in range(len(self.grids)):
+            t = L.ExxTuning()
+            L.check(L.lib().exx_batch_get_tuning(self._h, s, C.byref(t)), "exx_batch_get_tuning")
+            out.append({"tile": t.tile, "batch_slots": t.batch_slots, "slab_threads": t.slab_threads,
+                        "streams": t.streams, "slab_form": t.slab_form})
+        return out
+
     def compute(self, psis, occs, mode: str = "energy_kpsi", outputs=None):
         """psis/occs: lists of device tensors; returns a list of (E_x, K psi) per system.
 
@@ -64,17 +102,7 @@ class Batch:
                 ex = torch.empty((), dtype=torch.float64, device=self.device)
                 kp = torch.empty_like(psis[s]) if m & L.MODE_KPSI else None
                 outputs.append((ex, kp))
-        sysarr = (L.ExxSystem * S)()
-        for s in range(S):
-            n = self.grids[s].n
-            _check_tensor("psi", psis[s], (self.n_orb[s], n, n, n), self.device, self.dtype)
-            _check_tensor("occ", occs[s], (self.n_orb[s],), self.device)
-            ex, kp = outputs[s]
-            sysarr[s].psi = psis[s].data_ptr()
-            sysarr[s].occ = occs[s].data_ptr()
-            sysarr[s].ex_out = ex.data_ptr() if (m & L.MODE_ENERGY) else None
-            sysarr[s].kpsi = kp.data_ptr() if kp is not None else None
-            sysarr[s].pair_e = None
+        sysarr = self._systems(psis, occs, outputs, m)
         with torch.cuda.device(self.device):
             rc = L.lib().exx_batch_compute(self._h, sysarr, m, 0, self.ws.data_ptr(), self.ws.numel(),
                                            _stream_ptr(self.device))

@@ -727,6 +727,25 @@ int exx_compute(exx_plan* p, const double* psi, const double* occ, int n_orb, in
                            stream, true);
 }
 
+int exx_gradient(exx_plan* p, const double* psi, const double* occ, int n_orb,
+                 const double* gbar, double* grad_psi, double* grad_occ, double* pair_e, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
+  if (!gbar || !grad_psi) return fail(EXX_ERR_INVALID_ARG, "gbar and grad_psi are required");
+  if (grad_occ && !pair_e) return fail(EXX_ERR_INVALID_ARG, "grad_occ needs the pair_e buffer");
+  if (!aligned(gbar, 8) || (grad_occ && !aligned(grad_occ, 8)))
+    return fail(EXX_ERR_ALIGNMENT, "gbar and grad_occ must be 8-byte aligned");
+  // K psi (and the pair energies when the occupation gradient is wanted) into
+  // the output buffers, then the scaling in place on the same stream
+  const int rc = exx::compute_impl(p, psi, occ, n_orb, EXX_MODE_KPSI, 0, nullptr, grad_psi,
+                                   grad_occ ? pair_e : nullptr, ws, ws_bytes, stream, true);
+  if (rc) return rc;
+  const size_t per_orb = (size_t)p->n * p->n * p->n * (p->cplx ? 2 : 1);
+  EXX_HIP(launch_gradient(grad_psi, per_orb, n_orb, occ, gbar, p->h3, pair_e, grad_occ,
+                          static_cast<hipStream_t>(stream)));
+  return EXX_OK;
+}
+
 int exx_plan_enable_profiling(exx_plan* p, int enable) {
   if (!p) return fail(EXX_ERR_INVALID_ARG, "plan is NULL");
   p->profile = enable != 0;

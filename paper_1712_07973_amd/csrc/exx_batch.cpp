@@ -211,6 +211,75 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
   return EXX_OK;
 }
 
+int exx_batch_autotune(exx_batch* b, const exx_system* sys, void* ws, size_t ws_bytes,
+                       void* stream, int budget_ms, const char* cache_path) {
+  if (!b || !sys) return record_error(EXX_ERR_INVALID_ARG, "batch or systems is NULL");
+  if (!ws || ws_bytes < b->ws_total)
+    return record_error(EXX_ERR_WORKSPACE, "workspace smaller than exx_batch_workspace_bytes(): need " +
+                                               std::to_string(b->ws_total));
+  const size_t n = b->plans.size();
+  // classes: systems on the same grid (same kernels and kernel table); each is
+  // tuned on its member with the most orbitals
+  auto same_grid = [&](size_t a, size_t c) {
+    const exx_grid& ga = b->plans[a]->grid;
+    const exx_grid& gc = b->plans[c]->grid;
+    return ga.nx == gc.nx && ga.ny == gc.ny && ga.nz == gc.nz && ga.hx == gc.hx && ga.hy == gc.hy &&
+           ga.hz == gc.hz && ga.bc == gc.bc && ga.kernel == gc.kernel && ga.R == gc.R &&
+           ga.omega == gc.omega && b->plans[a]->precision == b->plans[c]->precision;
+  };
+  std::vector<int> cls(n, -1);
+  std::vector<size_t> rep;
+  for (size_t s = 0; s < n; ++s) {
+    if (cls[s] >= 0) continue;
+    cls[s] = (int)rep.size();
+    size_t best = s;
+    for (size_t c = s + 1; c < n; ++c)
+      if (cls[c] < 0 && same_grid(s, c)) {
+        cls[c] = cls[s];
+        if (b->n_orb[c] > b->n_orb[best]) best = c;
+      }
+    rep.push_back(best);
+  }
+  const int per_class = std::max(1, (budget_ms > 0 ? budget_ms : 20000) / (int)rep.size());
+  char* wsc = static_cast<char*>(ws);
+  for (size_t k = 0; k < rep.size(); ++k) {
+    const size_t s = rep[k];
+    if (!sys[s].kpsi)
+      return record_error(EXX_ERR_INVALID_ARG, "exx_batch_autotune needs each class's K psi buffer as scratch");
+    const size_t slice = (s + 1 < n ? b->ws_off[s + 1] : b->ws_total) - b->ws_off[s];
+    int rc = exx_autotune(b->plans[s], sys[s].psi, sys[s].occ, b->n_orb[s], sys[s].kpsi,
+                          wsc + b->ws_off[s], slice, stream, per_class, cache_path);
+    if (rc != EXX_OK) return rc;
+    exx_tuning t{};
+    exx_plan_get_tuning(b->plans[s], &t);
+    for (size_t c = 0; c < n; ++c) {
+      if (cls[c] != (int)k || c == s) continue;
+      // the class's tuning where it fits this member's share of the workspace
+      exx_tuning old{};
+      exx_plan_get_tuning(b->plans[c], &old);
+      rc = exx_plan_set_tuning(b->plans[c], &t);
+      size_t need = 0;
+      const size_t share = (c + 1 < n ? b->ws_off[c + 1] : b->ws_total) - b->ws_off[c];
+      if (rc == EXX_OK) rc = exx_workspace_bytes(b->plans[c], b->n_orb[c], &need);
+      if (rc != EXX_OK || need > share) (void)exx_plan_set_tuning(b->plans[c], &old);
+      rc = exx_plan_prepare(b->plans[c], b->n_orb[c]);
+      if (rc != EXX_OK) return rc;
+    }
+  }
+  // the captured graph holds the old launches: capture again on the next call
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  return EXX_OK;
+}
+
+int exx_batch_get_tuning(const exx_batch* b, int system, exx_tuning* out) {
+  if (!b || !out || system < 0 || system >= (int)b->plans.size())
+    return record_error(EXX_ERR_INVALID_ARG, "batch, system index or out is invalid");
+  return exx_plan_get_tuning(b->plans[system], out);
+}
+
 int exx_autotune(exx_plan* p, const double* psi, const double* occ, int n_orb, double* kpsi,
                  void* ws, size_t ws_bytes, void* stream, int budget_ms, const char* cache_path) {
   if (!p || !psi || !occ || !kpsi) return record_error(EXX_ERR_INVALID_ARG, "plan, psi, occ and kpsi are required");

@@ -770,6 +770,18 @@ __global__ __launch_bounds__(NT, (pass_b_min_waves<T, N, NT, SHARE_Y>())) void k
 // between the two steps sit at row p ^ ((p / 8) & 3) of their column instead
 // of row p = t + 8 q1, which keeps both steps' accesses free of bank conflicts.
 // ---------------------------------------------------------------------------
+// LDS load of one complex value that the compiler keeps as a single 8-byte
+// (16-byte for FP64) read: on gfx950 a paired read (ds_read2_b64) of two such
+// values measured 7.3 LDS cycles against 2 x 2.1 for two single reads, and
+// pairing is what the compiler does with nearby addresses of one base.
+template <typename T>
+__device__ __forceinline__ cpx<T> lds_ld(const cpx<T>* p) {
+  using V2 = T __attribute__((ext_vector_type(2)));
+  using LV = __attribute__((address_space(3))) volatile V2;
+  const V2 v = *(const LV*)(p);  // generic -> LDS address space
+  return {v.x, v.y};
+}
+
 template <int N>
 constexpr int wave_pitch() {
   int p = 9 * N / 8;
@@ -854,7 +866,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
     for (int k1 = 0; k1 < L1; ++k1) {
       const cpx<T> a = buffer_load_cpx<T>(grs, goff, k1 * KSTRIDE);
-      v[k1] = CYI ? cmul(a, md[ty + 8 * k1]) : a;
+      v[k1] = CYI ? cmul(a, lds_ld(&md[ty + 8 * k1])) : a;
     }
     if constexpr (CYI == 1 && !EONLY && !HOLD) {
       // the class-1 input is in registers: park the class-0 output in the slab
@@ -863,7 +875,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
     }
     Dft<L1, -1, T>::run(v);
 #pragma unroll
-    for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], tw[q1 * 8 + ty]);
+    for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], lds_ld(&tw[q1 * 8 + ty]));
 #pragma unroll
     for (int q1 = 0; q1 < L1; ++q1) Scol[((ty ^ (q1 & 3)) + 8 * q1) * PB] = v[q1];
   }
@@ -876,7 +888,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
       const int q1 = ty + 8 * j;
       if (q1 < L1) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) w[j][t] = Scol[((t ^ (ty & 3)) + 8 * q1) * PB];
+        for (int t = 0; t < 8; ++t) w[j][t] = lds_ld(&Scol[((t ^ (ty & 3)) + 8 * q1) * PB]);
       }
     }
     wave_lds_sync();  // every lane's reads precede the in-place writes
@@ -907,7 +919,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
         if (q1 < L1) {
           cpx<T> w[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) w[t] = Srow[t + 9 * q1];
+          for (int t = 0; t < 8; ++t) w[t] = lds_ld(&Srow[t + 9 * q1]);
           Dft<8, -1, T>::run(w);
           // kernel index kzf = c + step q2: below half the range fold(kzf) = kzf,
           // above it MZ - kzf, switching exactly at q2 = 4
@@ -929,7 +941,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
           if (!EONLY) {
             Dft<8, 1, T>::run(w);
 #pragma unroll
-            for (int t = 1; t < 8; ++t) w[t] = cmulc(w[t], tw[q1 * 8 + t]);
+            for (int t = 1; t < 8; ++t) w[t] = cmulc(w[t], lds_ld(&tw[q1 * 8 + t]));
 #pragma unroll
             for (int t = 0; t < 8; ++t) Srow[t + 9 * q1] = w[t];
           }
@@ -941,19 +953,19 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
       cpx<T> u0[L1];
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
-        u0[k1] = Srow[tz + 9 * k1];
-        if constexpr (CZ == 2) u1[k1] = cmul(u0[k1], md[tz + 8 * k1]);
+        u0[k1] = lds_ld(&Srow[tz + 9 * k1]);
+        if constexpr (CZ == 2) u1[k1] = cmul(u0[k1], lds_ld(&md[tz + 8 * k1]));
       }
       Dft<L1, -1, T>::run(u0);
 #pragma unroll
-      for (int q1 = 1; q1 < L1; ++q1) u0[q1] = cmul(u0[q1], tw[q1 * 8 + tz]);
+      for (int q1 = 1; q1 < L1; ++q1) u0[q1] = cmul(u0[q1], lds_ld(&tw[q1 * 8 + tz]));
 #pragma unroll
       for (int q1 = 0; q1 < L1; ++q1) Srow[tz + 9 * q1] = u0[q1];
     }
     if constexpr (CZ == 2) {
       Dft<L1, -1, T>::run(u1);
 #pragma unroll
-      for (int q1 = 1; q1 < L1; ++q1) u1[q1] = cmul(u1[q1], tw[q1 * 8 + tz]);
+      for (int q1 = 1; q1 < L1; ++q1) u1[q1] = cmul(u1[q1], lds_ld(&tw[q1 * 8 + tz]));
     }
     wave_lds_sync();
     z_mid(0);
@@ -962,7 +974,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
     if constexpr (!EONLY) {
       // inverse step 1 of class 0: IDFT_L1 over q1 -> z = tz + 8 k1
 #pragma unroll
-      for (int q1 = 0; q1 < L1; ++q1) acc[q1] = Srow[tz + 9 * q1];
+      for (int q1 = 0; q1 < L1; ++q1) acc[q1] = lds_ld(&Srow[tz + 9 * q1]);
       Dft<L1, 1, T>::run(acc);
     }
     if constexpr (CZ == 2) {
@@ -975,10 +987,10 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
       if constexpr (!EONLY) {
         cpx<T> v[L1];
 #pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) v[q1] = Srow[tz + 9 * q1];
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds_ld(&Srow[tz + 9 * q1]);
         Dft<L1, 1, T>::run(v);
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) acc[k1] = cadd(acc[k1], cmulc(v[k1], md[tz + 8 * k1]));
+        for (int k1 = 0; k1 < L1; ++k1) acc[k1] = cadd(acc[k1], cmulc(v[k1], lds_ld(&md[tz + 8 * k1])));
       }
     }
     if constexpr (EONLY) {
@@ -1003,7 +1015,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
       const int q1 = ty2 + 8 * j;
       if (q1 < L1) {
 #pragma unroll
-        for (int q2 = 0; q2 < 8; ++q2) w[j][q2] = Scol2[(q1 + L1 * q2) * PB];
+        for (int q2 = 0; q2 < 8; ++q2) w[j][q2] = lds_ld(&Scol2[(q1 + L1 * q2) * PB]);
       }
     }
     wave_lds_sync();
@@ -1013,7 +1025,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
       if (q1 < L1) {
         Dft<8, 1, T>::run(w[j]);
 #pragma unroll
-        for (int t = 1; t < 8; ++t) w[j][t] = cmulc(w[j][t], tw[q1 * 8 + t]);
+        for (int t = 1; t < 8; ++t) w[j][t] = cmulc(w[j][t], lds_ld(&tw[q1 * 8 + t]));
 #pragma unroll
         for (int t = 0; t < 8; ++t) Scol2[((t ^ (ty2 & 3)) + 8 * q1) * PB] = w[j][t];
       }
@@ -1024,10 +1036,10 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
   {
     cpx<T> o[L1];
 #pragma unroll
-    for (int q1 = 0; q1 < L1; ++q1) o[q1] = Scol2[((ty2 ^ (q1 & 3)) + 8 * q1) * PB];
+    for (int q1 = 0; q1 < L1; ++q1) o[q1] = lds_ld(&Scol2[((ty2 ^ (q1 & 3)) + 8 * q1) * PB]);
     Dft<L1, 1, T>::run(o);
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) o[k1] = CYI ? cmulc(o[k1], md[ty2 + 8 * k1]) : o[k1];
+    for (int k1 = 0; k1 < L1; ++k1) o[k1] = CYI ? cmulc(o[k1], lds_ld(&md[ty2 + 8 * k1])) : o[k1];
     if constexpr (CY == 2 && CYI == 0) {
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) P[k1] = o[k1];
@@ -1428,6 +1440,20 @@ constexpr int pass_c_min_waves() {
   return (sizeof(T) == 4 && N <= 32) ? 3 : 1;
 }
 
+// b where the mask is all ones, a where it is zero, bit by bit.  The mask comes
+// through opaque(), so the compiler cannot turn the choice between two elements
+// of a register array into one load at a run-time index (a stack array).
+template <typename T>
+__device__ __forceinline__ T pick(unsigned m, T a, T b) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
+  } else {
+    const unsigned long long m2 = ((unsigned long long)m << 32) | m;
+    return __longlong_as_double((long long)(((unsigned long long)__double_as_longlong(a) & ~m2) |
+                                            ((unsigned long long)__double_as_longlong(b) & m2)));
+  }
+}
+
 template <typename T, int N, int NCLS, int ZB, int NT, int TM, int HP>
 __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const cpx<T>* __restrict__ X,
                                                const T* __restrict__ psi,
@@ -1463,10 +1489,9 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   __shared__ double fI[TM], fJ[TM];
   __shared__ double ered[MAXS][2][NW];
   __shared__ double etot[NW];
-  // J-side orbital values at the owned points: LDS when one thread owns a
-  // segment, registers when it owns half of one
-  __shared__ T pJs[HP == 1 ? TM : 1][HP == 1 ? L1 * NT : 1];
-  T pJr[HP == 2 ? TM : 1][HP == 2 ? LP : 1];
+  // J-side orbital values at the owned points (slot [b][k1 NT + tid], read back
+  // by the same thread only)
+  __shared__ T pJs[TM][LP * NT];
 
   const int tid = threadIdx.x;
   const int y = blockIdx.x / (N / ZB);
@@ -1478,6 +1503,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   const int h_own = tid / (ZB * L2), rt = tid % (ZB * L2);
   const int t_own = rt % L2, zi_own = rt / L2;
   const int k0 = h_own * LP;
+  const unsigned hmask = opaque(h_own ? ~0u : 0u);  // second half of a segment
   // offset of the owned row (swap_yz: spectrum (y, z) = grid (z, y))
   const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
   const int ns = tp.s1 - tp.s0;
@@ -1525,13 +1551,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     if (b >= tp.nJ) continue;
     const T* po = psi + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
-    for (int k1 = 0; k1 < LP; ++k1) {
-      const T v = po[t_own + L2 * (k0 + k1)];
-      if constexpr (HP == 1)
-        pJs[b][k1 * NT + tid] = v;
-      else
-        pJr[b][k1] = v;
-    }
+    for (int k1 = 0; k1 < LP; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * (k0 + k1)];
   }
   __syncthreads();
   if (ns > 0) fetch(0);
@@ -1589,14 +1609,18 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
         for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
         Dft<L1, 1, T>::run(v);
 #pragma unroll
-        for (int k1 = 0; k1 < LP; ++k1) V[k1] = HP == 1 ? v[k1] : (h_own ? v[LP + k1] : v[k1]);
+        for (int k1 = 0; k1 < LP; ++k1)
+          V[k1] = HP == 1 ? v[k1]
+                          : cpx<T>{pick(hmask, v[k1].x, v[LP % L1 + k1].x), pick(hmask, v[k1].y, v[LP % L1 + k1].y)};
         if (NCLS == 2) {
 #pragma unroll
           for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
           Dft<L1, 1, T>::run(v);
 #pragma unroll
           for (int k1 = 0; k1 < LP; ++k1) {
-            const cpx<T> w = HP == 1 ? v[k1] : (h_own ? v[LP + k1] : v[k1]);
+            const cpx<T> w = HP == 1 ? v[k1]
+                                     : cpx<T>{pick(hmask, v[k1].x, v[LP % L1 + k1].x),
+                                              pick(hmask, v[k1].y, v[LP % L1 + k1].y)};
             V[k1] = cadd(V[k1], cmulc(w, md[t_own + L2 * (k0 + k1)]));
           }
         }
@@ -1614,12 +1638,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
         double e = 0.0;
 #pragma unroll
         for (int k1 = 0; k1 < LP; ++k1) {
-          const T pa = pI[k1];
-          T pb;
-          if constexpr (HP == 1)
-            pb = pJs[b][k1 * NT + tid];
-          else
-            pb = pJr[b][k1];
+          const T pa = pI[k1], pb = pJs[b][k1 * NT + tid];
           const double Vv = (double)(h ? V[k1].y : V[k1].x);
           e += (double)(pa * pb) * Vv;
           if (want_k) {
@@ -2037,6 +2056,57 @@ hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, cons
                            hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, slots, nvals, occ, e_slot, n_orb, h3,
                      sum_mode, ex_out, pair_e);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gradient of E_x (reverse mode).  E_x = -1/2 sum_ij f_i f_j e_ij with
+// e_ij = h^3 <rho_ij, V_ij> is a quartic in psi whose derivative with respect
+// to psi_k at a grid point is -2 f_k h^3 (K psi)_k (Eq. 3: K psi = -D_X psi),
+// and whose derivative with respect to f_k is -sum_j f_j e_kj.  Both are
+// scaled by the upstream derivative gbar (a device scalar, so the backward of
+// a captured or asynchronous evaluation needs no host sync).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_grad_psi(double* __restrict__ g, size_t per_orb,
+                                                  const double* __restrict__ occ,
+                                                  const double* __restrict__ gbar, double h3) {
+  const int k = blockIdx.y;
+  const double c = -2.0 * h3 * occ[k] * gbar[0];
+  double2* row = reinterpret_cast<double2*>(g + (size_t)k * per_orb);
+  const size_t n2 = per_orb / 2;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n2; i += (size_t)gridDim.x * 256) {
+    double2 v = row[i];
+    v.x *= c;
+    v.y *= c;
+    row[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_grad_occ(const double* __restrict__ pair_e, int n_orb,
+                                                  const double* __restrict__ occ,
+                                                  const double* __restrict__ gbar,
+                                                  double* __restrict__ g_occ) {
+  __shared__ double red[4];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int j = tid; j < n_orb; j += 256) s += occ[j] * pair_e[(size_t)k * n_orb + j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) g_occ[k] = -gbar[0] * (((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+hipError_t launch_gradient(double* grad_psi, size_t per_orb, int n_orb, const double* occ,
+                           const double* gbar, double h3, const double* pair_e, double* grad_occ,
+                           hipStream_t s) {
+  if (per_orb % 2 != 0) return hipErrorInvalidValue;  // rows are whole double2 runs
+  const size_t n2 = per_orb / 2;
+  const unsigned bx = (unsigned)std::min<size_t>((n2 + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_grad_psi, dim3(bx, n_orb), dim3(256), 0, s, grad_psi, per_orb, occ, gbar, h3);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !grad_occ) return e;
+  hipLaunchKernelGGL(k_grad_occ, dim3(n_orb), dim3(256), 0, s, pair_e, n_orb, occ, gbar, grad_occ);
   return hipGetLastError();
 }
 

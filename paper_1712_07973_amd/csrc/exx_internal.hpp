@@ -106,6 +106,11 @@ hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, cons
                            hipStream_t s);
 
 bool fused_supported(int precision, int n);
+// grad_psi[k] *= -2 h3 f_k gbar over per_orb doubles per orbital (even);
+// grad_occ (optional) = -gbar pair_e f
+hipError_t launch_gradient(double* grad_psi, size_t per_orb, int n_orb, const double* occ,
+                           const double* gbar, double h3, const double* pair_e, double* grad_occ,
+                           hipStream_t s);
 
 // Body of exx_compute.  may_allocate = false: no device allocation and no event
 // creation (the schedule for n_orb must already be prepared, profiling events

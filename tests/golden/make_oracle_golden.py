@@ -31,7 +31,7 @@ from exx_inputs import batch_recipes, make_system, recipe  # noqa: E402
 PLANS = {
     # preset: (full E and pair matrix?, number of sampled pairs, K psi rows, points per row)
     "free64_n32": (True, 0, [0, 7, 31], 2048),
-    "periodic96_n128": (False, 24, [3, 77], 2048),
+    "periodic96_n128": (True, 0, [3, 77], 2048),
     "free128_n256": (False, 12, [250], 2048),
     "surface64_n32": (True, 0, [0, 7, 31], 2048),
     "wire64_n32": (True, 0, [0, 7, 31], 2048),

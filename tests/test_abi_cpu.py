@@ -98,3 +98,9 @@ def test_null_plan_calls(lib):
     assert lib.exx_plan_prepare(None, 4) == -1
     lib.exx_plan_destroy(None)  # no-op
     assert lib.exx_batch_create(None, None, None, 0, 0, 0) == -1
+    assert lib.exx_compute_noalloc(None, None, None, 1, 3, 0, None, None, None, None) == -1
+    assert lib.exx_gradient(None, None, None, 1, None, None, None, None, None, 0, None) == -1
+    assert b"plan is NULL" in lib.exx_last_error()
+    assert lib.exx_batch_autotune(None, None, None, 0, None, 0, None) == -1
+    tun = L.ExxTuning()
+    assert lib.exx_batch_get_tuning(None, 0, C.byref(tun)) == -1

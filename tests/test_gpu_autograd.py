@@ -42,6 +42,35 @@ def test_backward_equals_oracle_gradient(precision):
     assert np.allclose(occ.grad.cpu().numpy(), go_ref, rtol=1e-11, atol=0)
 
 
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_plain"])
+def test_exx_gradient_with_an_upstream_factor(precision):
+    # exx_gradient through the C-ABI with gbar = -1.75 and a signed occupation,
+    # against the oracle gradient times gbar
+    say(f"[autograd] exx_gradient gbar {precision}")
+    s = small_system("periodic", 32, 4, seed=24)
+    occ_np = np.array([2.0, 1.5, -0.3, 0.8])
+    ref = oracle.exx(s.psi, occ_np, s.h, "periodic", symmetric=True)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(occ_np).to(dev)
+    plan = exx.Plan(grid_of(s), precision, n_orb_max=4)
+    gbar = torch.tensor(-1.75, dtype=torch.float64, device=dev)
+    gp, go = plan.gradient(psi, occ, gbar, want_occ=True)
+    torch.cuda.synchronize()
+    g_ref = -1.75 * oracle.exx_grad_psi(ref["kpsi"], occ_np, s.h)
+    go_ref = -1.75 * oracle.exx_grad_occ(ref["pair_e"], occ_np)
+    tol = TOL_FP32_K if precision == "fp32" else 1e-11
+    g = gp.cpu().numpy()
+    for k in range(4):
+        assert np.max(np.abs(g[k] - g_ref[k])) <= tol * np.max(np.abs(g_ref[k]))
+    # dE/df_k = -sum_j f_j e_kj: pair energies to 1e-6 (FP32) or 1e-12 of their
+    # largest value, summed with |f_j| weights
+    bound = (1e-6 if precision == "fp32" else 1e-12) * 1.75 * np.abs(occ_np).sum() * np.max(
+        np.abs(ref["pair_e"]))
+    assert np.max(np.abs(go.cpu().numpy() - go_ref)) <= bound
+
+
 def test_finite_differences_on_four_orbitals():
     say("[autograd] finite differences, periodic p-type")
     s = small_system("periodic", 32, 6, seed=31, ptype=True)
@@ -100,3 +129,55 @@ def test_fp32_backward_matches_fp64_backward():
     rel = np.linalg.norm((a - b).reshape(5, -1), axis=1) / np.linalg.norm(b.reshape(5, -1), axis=1)
     assert rel.max() < TOL_FP32_K
     assert np.allclose(out["fp32"][2], out["fp64_fused"][2], rtol=1e-6)
+
+
+@pytest.mark.timeout(600)
+def test_config3_finite_differences_and_fp32_backward():
+    # the periodic 96^3 system of 128 p-type orbitals (8256 pairs) at its own size:
+    # Richardson differences of the FP64 forward along directions that move one of
+    # 4 orbitals each, against the FP64 backward; then the FP32 backward against
+    # the oracle's stored K psi rows (dE/dpsi_k = -2 f_k h^3 (K psi)_k)
+    import os
+    from exx_inputs import system
+    say("[autograd] periodic96_n128: finite differences on 4 orbitals, FP32 backward")
+    s = system("periodic96_n128")
+    g = grid_of(s)
+    dev = torch.device("cuda", 0)
+    psi = torch.from_numpy(s.psi).to(dev)
+    occ = torch.from_numpy(s.occ).to(dev)
+    x = psi.clone().requires_grad_(True)
+    E = exx.exchange_energy(x, occ, g, "fp64_fused")
+    E.backward()
+    grad = x.grad.detach()
+    x.grad = None
+    rng = np.random.default_rng(96)
+    with torch.no_grad():
+        for k in (0, 31, 77, 127):
+            d = torch.zeros_like(psi)
+            d[k] = torch.from_numpy(rng.normal(size=s.psi.shape[1:])).to(dev)
+
+            def Ef(eps):
+                return exx.exchange_energy(psi + eps * d, occ, g, "fp64_fused").item()
+
+            def D(eps):
+                return (Ef(eps) - Ef(-eps)) / (2 * eps)
+
+            eps = 1e-3
+            fd = (4.0 * D(eps / 2) - D(eps)) / 3.0
+            an = float((grad[k] * d[k]).sum().item())
+            assert fd == pytest.approx(an, rel=1e-7), k
+    del grad
+    # FP32 backward at the stored oracle K psi rows
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "periodic96_n128_oracle.npz")
+    gold = dict(np.load(path))
+    x32 = psi.clone().requires_grad_(True)
+    E32 = exx.exchange_energy(x32, occ, g, "fp32")
+    E32.backward()
+    assert abs(E32.item() - E.item()) / s.n_orb < 1e-6
+    gk = x32.grad.detach().reshape(s.n_orb, -1)
+    pts = torch.from_numpy(gold["kpsi_points"]).to(dev)
+    for row, vals in zip(gold["kpsi_rows"], gold["kpsi_values"]):
+        want = -2.0 * s.occ[int(row)] * s.h ** 3 * vals
+        got = gk[int(row)].index_select(0, pts).cpu().numpy()
+        assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want))

@@ -117,6 +117,29 @@ def test_free128_n256_fp32():
     check("free128_n256", "fp32")
 
 
+@pytest.mark.timeout(900)
+def test_free128_n256_fp32_against_fp64_plain():
+    # E_x and every pair energy of the 256-orbital free system (32 896 pairs) with
+    # FP32 transforms against the plain FP64 path, which matches the oracle to
+    # 1e-12 on every smaller case; K psi compared at every point of 4 orbitals
+    say("[fullsize] free128_n256 fp32 against fp64_plain")
+    s = load_system("free128_n256")
+    r32 = evaluate(s, "fp32")
+    k32 = r32.pop("kpsi")
+    rows = [0, 100, 240, 255]
+    k32 = k32[rows].cpu().numpy()
+    torch.cuda.empty_cache()
+    r64 = evaluate(s, "fp64_plain")
+    k64 = r64.pop("kpsi")[rows].cpu().numpy()
+    dE = abs(r32["E"] - r64["E"]) / s.n_orb
+    say(f"  |dE_x|/N = {dE:.3e} Ha, E_x = {r64['E']:.12f}")
+    assert dE < 1e-6
+    scale = float(np.max(np.abs(r64["pair_e"])))
+    assert np.max(np.abs(r32["pair_e"] - r64["pair_e"])) <= 1e-5 * scale
+    for a, b in zip(k32, k64):
+        assert np.max(np.abs(a - b)) <= 1e-5 * np.max(np.abs(b))
+
+
 @pytest.mark.parametrize("sidx", [0, 5, 11])
 def test_batch16_members(sidx):
     check(f"batch16_s{sidx}", "fp32")

@@ -1,7 +1,7 @@
 """Turns rocprofv3 memory-counter runs into the traffic summary bench.py reads.
 
 Usage (after the two counter runs of the bench and of its copy probe):
-  python -m paper_1712_07973_amd.traffic_summary <fetch_bench_dir> <write_bench_dir> \
+  python traffic_summary.py <fetch_bench_dir> <write_bench_dir> \
       <fetch_copy_dir> <write_copy_dir> <kernel> <workload> <launches_per_step>
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Each is scaled by
@@ -17,7 +17,7 @@ import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 COPY_BYTES = 1 << 30
 
 
