@@ -835,13 +835,18 @@ template <typename T, int N, int CX, int CY, int CZ, bool EONLY, int CYI>
 __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T>* __restrict__ tw,
                                              const cpx<T>* __restrict__ md, cpx<T>* g,
                                              __amdgpu_buffer_rsrc_t grs, const T* kt,
-                                             cpx<T> (&P)[N / 8], double& esum) {
+                                             cpx<T> (&P)[N / 8], cpx<T> (&V1)[N / 8],
+                                             double& esum) {
   constexpr int L1 = N / 8, PB = wave_pitch<N>();
   constexpr int NJ = (L1 + 7) / 8;  // step-2 items per lane
   constexpr int MY = CY * N, MZ = CZ * N;
   constexpr int HZ = MZ / 2 + 1;
   constexpr bool PADY = CY == 2, PADZ = CZ == 2;
   constexpr bool HOLD = wave_hold_p0<T, N>();
+  // with two y classes the class-1 input is loaded during class 0's inverse y
+  // phase, and (n > 64) the parked class-0 result during class 1's, so that
+  // their latency overlaps the inverse transforms
+  constexpr bool EARLY = CY == 2 && !EONLY;
   constexpr unsigned KSTRIDE = 8u * CX * N * N * sizeof(cpx<T>);  // slab rows y -> y + 8
 
   // lane coordinates, laundered per class (see opaque)
@@ -865,7 +870,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
     cpx<T> v[L1];
 #pragma unroll
     for (int k1 = 0; k1 < L1; ++k1) {
-      const cpx<T> a = buffer_load_cpx<T>(grs, goff, k1 * KSTRIDE);
+      const cpx<T> a = (EARLY && CYI == 1) ? V1[k1] : buffer_load_cpx<T>(grs, goff, k1 * KSTRIDE);
       v[k1] = CYI ? cmul(a, lds_ld(&md[ty + 8 * k1])) : a;
     }
     if constexpr (CYI == 1 && !EONLY && !HOLD) {
@@ -910,9 +915,29 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
   {
     const int kyf = PADY ? 2 * kr + CYI : kr;
     const T* krow = kt + (size_t)fold(kyf, MY) * HZ;
+    // kernel values of one z class at this lane's (q1 = tz + 8 j, q2): kernel
+    // index kzf = c + step q2; below half the range fold(kzf) = kzf, above it
+    // MZ - kzf, switching exactly at q2 = 4.  Where the registers allow it
+    // (FP32 except n = 112, which then spills) they are loaded ahead of their
+    // use, so the latency overlaps the transforms; else where they are used.
+    constexpr int step = PADZ ? 2 * L1 : L1;
+    constexpr bool KPRE = sizeof(T) == 4 && N != 112;
+    auto k_load = [&](int cz, auto& kv) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int q1 = tz + 8 * j;
+        if (q1 < L1) {
+          const int c = PADZ ? 2 * q1 + cz : q1;
+          const T* k_lo = krow + c;
+          const T* k_hi = krow + (MZ - c);
+#pragma unroll
+          for (int q2 = 0; q2 < 8; ++q2) kv[j][q2] = (q2 < 4) ? k_lo[step * q2] : k_hi[-step * q2];
+        }
+      }
+    };
     // step 2 of one class, in place in the row: per q1 = tz + 8 j, DFT_8,
     // kernel (kz = q1 + L1 q2) or the Parseval sum, inverse DFT_8
-    auto z_mid = [&](int cz) {
+    auto z_mid = [&](int cz, const auto& kv) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
         const int q1 = tz + 8 * j;
@@ -921,21 +946,20 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
           for (int t = 0; t < 8; ++t) w[t] = lds_ld(&Srow[t + 9 * q1]);
           Dft<8, -1, T>::run(w);
-          // kernel index kzf = c + step q2: below half the range fold(kzf) = kzf,
-          // above it MZ - kzf, switching exactly at q2 = 4
-          constexpr int step = PADZ ? 2 * L1 : L1;
-          const int c = PADZ ? 2 * q1 + cz : q1;
-          const T* k_lo = krow + c;
-          const T* k_hi = krow + (MZ - c);
 #pragma unroll
           for (int q2 = 0; q2 < 8; ++q2) {
-            const T kv = (q2 < 4) ? k_lo[step * q2] : k_hi[-step * q2];
-            if (EONLY) {
-              esum += (double)kv * ((double)w[q2].x * (double)w[q2].x +
-                                    (double)w[q2].y * (double)w[q2].y);
+            T k;
+            if constexpr (KPRE) {
+              k = kv[j][q2];
             } else {
-              w[q2].x *= kv;
-              w[q2].y *= kv;
+              const int c = PADZ ? 2 * q1 + cz : q1;
+              k = (q2 < 4) ? krow[c + step * q2] : krow[MZ - c - step * q2];
+            }
+            if (EONLY) {
+              esum += (double)k * ((double)w[q2].x * (double)w[q2].x + (double)w[q2].y * (double)w[q2].y);
+            } else {
+              w[q2].x *= k;
+              w[q2].y *= k;
             }
           }
           if (!EONLY) {
@@ -948,6 +972,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
         }
       }
     };
+    T kv0[KPRE ? NJ : 1][8], kv1[KPRE && CZ == 2 ? NJ : 1][8];
     cpx<T> u1[CZ == 2 ? L1 : 1];
     {
       cpx<T> u0[L1];
@@ -962,13 +987,15 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
       for (int q1 = 0; q1 < L1; ++q1) Srow[tz + 9 * q1] = u0[q1];
     }
+    if constexpr (KPRE) k_load(0, kv0);
     if constexpr (CZ == 2) {
       Dft<L1, -1, T>::run(u1);
 #pragma unroll
       for (int q1 = 1; q1 < L1; ++q1) u1[q1] = cmul(u1[q1], lds_ld(&tw[q1 * 8 + tz]));
     }
     wave_lds_sync();
-    z_mid(0);
+    z_mid(0, kv0);
+    if constexpr (CZ == 2 && KPRE) k_load(1, kv1);
     wave_lds_sync();  // step 2 of class 0 precedes the reads and stores below
     cpx<T> acc[L1];
     if constexpr (!EONLY) {
@@ -982,7 +1009,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
       for (int q1 = 0; q1 < L1; ++q1) Srow[tz + 9 * q1] = u1[q1];
       wave_lds_sync();
-      z_mid(1);
+      z_mid(1, kv1);
       wave_lds_sync();
       if constexpr (!EONLY) {
         cpx<T> v[L1];
@@ -1008,6 +1035,20 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
   const unsigned tid2 = opaque(threadIdx.x);
   const int zc2 = 8 * (int)(tid2 >> 6) + (int)(tid2 & 7), ty2 = (int)((tid2 & 63) >> 3);
   cpx<T>* Scol2 = S + (zc2 + (zc2 >> 3));
+  const unsigned off2 = (unsigned)(((size_t)ty2 * CX * N * N + (size_t)(zc2 / XZ) * (CX * N * XZ) +
+                                    zc2 % XZ) * sizeof(cpx<T>));
+  cpx<T> pk[EARLY && CYI == 1 && !HOLD ? L1 : 1];
+  if constexpr (EARLY) {
+    // no workgroup barrier remains before these values are used, so nothing
+    // forces the loads to complete before the transforms below
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1) {
+      if constexpr (CYI == 0)
+        V1[k1] = buffer_load_cpx<T>(grs, off2, k1 * KSTRIDE);  // the class-1 input
+      else if constexpr (!HOLD)
+        pk[k1] = buffer_load_cpx<T>(grs, off2, k1 * KSTRIDE);  // the parked class-0 result
+    }
+  }
   {
     cpx<T> w[NJ][8];
 #pragma unroll
@@ -1044,12 +1085,10 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) P[k1] = o[k1];
     } else {
-      const unsigned off = (unsigned)(((size_t)ty2 * CX * N * N + (size_t)(zc2 / XZ) * (CX * N * XZ) +
-                                       zc2 % XZ) * sizeof(cpx<T>));
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
-        cpx<T>* dst = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(g) + off + (size_t)k1 * KSTRIDE);
-        if (CY == 2) o[k1] = cadd(o[k1], HOLD ? P[k1] : *dst);
+        cpx<T>* dst = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(g) + off2 + (size_t)k1 * KSTRIDE);
+        if (CY == 2) o[k1] = cadd(o[k1], HOLD ? P[k1] : pk[(EARLY && !HOLD) ? k1 : 0]);
         *dst = o[k1];
       }
     }
@@ -1090,9 +1129,9 @@ __global__ __launch_bounds__(8 * N) void k_pass_b_wave(cpx<T>* __restrict__ X,
   __syncthreads();
 
   double esum = 0.0;
-  cpx<T> P[L1];
-  wave_y_class<T, N, CX, CY, CZ, EONLY, 0>(S, tw, md, g, grs, kt, P, esum);
-  if constexpr (CY == 2) wave_y_class<T, N, CX, CY, CZ, EONLY, 1>(S, tw, md, g, grs, kt, P, esum);
+  cpx<T> P[L1], V1[L1];
+  wave_y_class<T, N, CX, CY, CZ, EONLY, 0>(S, tw, md, g, grs, kt, P, V1, esum);
+  if constexpr (CY == 2) wave_y_class<T, N, CX, CY, CZ, EONLY, 1>(S, tw, md, g, grs, kt, P, V1, esum);
 
   if constexpr (EONLY) {
     // block reduction of the Parseval sum into this (slot, slab)'s partial
@@ -1428,9 +1467,13 @@ constexpr int pass_c_halves() {
   return (sizeof(T) == 4 && N > 64 && (N / 16) % 2 == 0) ? 2 : 1;
 }
 
-template <typename T, int N>
-constexpr int pass_c_tile() {  // K psi register budget: (tile + 1) * L1 / HP FP64 values per thread
-  return (N / 16 <= 4 || pass_c_halves<T, N>() == 2) ? 8 : 4;
+// pair-tile edge of the variant with HP threads per segment: the K psi register
+// budget is (tile + 1) L1 / HP FP64 values per thread.  Where two threads per
+// segment are possible a schedule tile above the one-thread tile selects them,
+// so a tile of 4 at n = 96, 128 runs the one-thread, 256-thread variant.
+template <typename T, int N, int HP = pass_c_halves<T, N>()>
+constexpr int pass_c_tile() {
+  return (N / 16 <= 4 || HP == 2) ? 8 : 4;
 }
 
 // FP32 at n <= 32: ask for 3 waves per SIMD (168 registers); larger grids
@@ -2382,9 +2425,6 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
       return hipErrorInvalidValue;
     } else {
       constexpr int ZB = XZ;
-      constexpr int HP = pass_c_halves<T, N>();
-      constexpr int NT = ZB * 16 * HP;
-      constexpr int TM = pass_c_tile<T, N>();
       dim3 grid(N * (N / ZB), ntiles);
       auto* Xc = static_cast<const cpx<T>*>(X);
       auto* tw = static_cast<const cpx<T>*>(tb.tw);
@@ -2404,16 +2444,24 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
                              want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
         return hipGetLastError();
       }
-      if (tmax > TM) return hipErrorInvalidValue;
-      if (L.ncls == 2)
-        hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc, psi,
-                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
-                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
-      else
-        hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc, psi,
-                           occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
-                           want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
-      return hipGetLastError();
+      auto run = [&]<int HP>() -> hipError_t {
+        constexpr int NT = ZB * 16 * HP;
+        constexpr int TM = pass_c_tile<T, N, HP>();
+        if (tmax > TM) return hipErrorInvalidValue;
+        if (L.ncls == 2)
+          hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc,
+                             psi, occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
+        else
+          hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc,
+                             psi, occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
+        return hipGetLastError();
+      };
+      if constexpr (pass_c_halves<T, N>() == 2) {
+        if (tmax > pass_c_tile<T, N, 1>()) return run.template operator()<2>();
+      }
+      return run.template operator()<1>();
     }
   });
 }

@@ -34,6 +34,7 @@ def small_system(bc: str, n: int, N: int, seed: int, frac: int = 0, ptype: bool 
 
 
 @functools.lru_cache(maxsize=None)
+@functools.lru_cache(maxsize=4)
 def oracle_result(bc: str, n: int, N: int, seed: int, frac: int = 0, ptype: bool = False,
                   kmax: float = 0.0):
     s = small_system(bc, n, N, seed, frac, ptype, kmax=kmax)

@@ -102,3 +102,34 @@ def test_single_plan_captured_in_a_torch_graph(complex_orbitals):
         assert np.array_equal(kpsi.cpu().numpy(), K0)
         x = torch.randn(1 << 20, device=dev)
         (x * 2).sum().item()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_autotune_per_grid_class(use_graph):
+    # exx_batch_autotune tunes one member per grid class and gives every member of
+    # the class the same tuning; each member then equals a single-system plan
+    # with that tuning, bit for bit, on every replay
+    say(f"[batch autotune] graph={use_graph}")
+    dev = torch.device("cuda", 0)
+    cases = [("free", 32, 9, 46), ("free", 48, 6, 47), ("free", 32, 5, 48), ("periodic", 32, 4, 49)]
+    systems = [small_system(bc, n, N, seed) for bc, n, N, seed in cases]
+    psis = [torch.from_numpy(s.psi).to(dev) for s in systems]
+    occs = [torch.from_numpy(s.occ).to(dev) for s in systems]
+    b = exx.Batch([grid_of(s) for s in systems], [s.n_orb for s in systems], "fp32",
+                  use_graph=use_graph)
+    outs = b.compute(psis, occs, "energy_kpsi")
+    torch.cuda.synchronize()
+    tunings = b.autotune(psis, occs, budget_ms=3000)
+    assert tunings[0] == tunings[2]  # the two free 32^3 systems share one class
+    outs = b.compute(psis, occs, "energy_kpsi", outputs=outs)
+    torch.cuda.synchronize()
+    for rep in range(2):
+        outs = b.compute(psis, occs, "energy_kpsi", outputs=outs)
+        torch.cuda.synchronize()
+        for s, p, o, t, (ex, kp) in zip(systems, psis, occs, tunings, outs):
+            plan = exx.Plan(grid_of(s), "fp32", n_orb_max=s.n_orb)
+            plan.set_tuning(**t)
+            e1, k1, _ = plan.compute(p, o, "energy_kpsi")
+            torch.cuda.synchronize()
+            assert ex.item() == e1.item()
+            assert torch.equal(kp, k1)

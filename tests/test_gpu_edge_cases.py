@@ -11,7 +11,9 @@
 * an orbital with zero occupation (it still receives K psi, contributes none);
 * batches of real-orbital systems against the oracle, not only against
   single-system calls;
-* a negative occupation in the energy-only mode (signed weights kept).
+* a negative occupation in the energy-only mode (signed weights kept);
+* both thread splits of pass C at n = 96 and 128 (tile 4: one thread per row
+  segment; tile 8: two).
 """
 import numpy as np
 import pytest
@@ -72,6 +74,23 @@ def test_slab_forms_match_oracle(case, form):
     torch.cuda.synchronize()
     _check(s, ref, ex.item(), kpsi.cpu().numpy(), pe.cpu().numpy(), "fp32", N)
     assert abs(e2.item() - ref["E"]) / N < TOL_FP32_E_PER_ORB
+
+
+@pytest.mark.parametrize("tile", [4, 8])
+@pytest.mark.parametrize("bc,n,N,seed", [("free", 96, 6, 81), ("free", 128, 5, 82),
+                                         ("periodic", 128, 5, 83)])
+def test_pass_c_thread_split_matches_oracle(bc, n, N, seed, tile):
+    # at n = 96, 128 a tile of 4 runs pass C with one thread per row segment
+    # (256 threads), a tile of 8 with two threads per segment (512 threads)
+    say(f"[pass C split] fp32 tile={tile} {bc} n={n} N={N} seed={seed}")
+    s, ref = oracle_result(bc, n, N, seed, 1)
+    psi, occ = _tensors(s)
+    plan = exx.Plan(grid_of(s), "fp32", n_orb_max=N)
+    plan.set_tuning(tile=tile)
+    pe = torch.empty((N, N), dtype=torch.float64, device=DEV)
+    ex, kpsi, pe = plan.compute(psi, occ, "energy_kpsi", pair_e=pe)
+    torch.cuda.synchronize()
+    _check(s, ref, ex.item(), kpsi.cpu().numpy(), pe.cpu().numpy(), "fp32", N)
 
 
 @pytest.mark.parametrize("case", [c for c in FORM_CASES if c[1] <= 80],
