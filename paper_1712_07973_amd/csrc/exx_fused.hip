@@ -782,6 +782,56 @@ __device__ __forceinline__ cpx<T> lds_ld(const cpx<T>* p) {
   return {v.x, v.y};
 }
 
+// Two consecutive complex values (16-byte aligned) in one 16-byte LDS read.
+template <typename T>
+__device__ __forceinline__ void lds_ld2(const cpx<T>* p, cpx<T>& a, cpx<T>& b) {
+  using V4 = T __attribute__((ext_vector_type(4)));
+  using LV = __attribute__((address_space(3))) volatile V4;
+  const V4 v = *(const LV*)(p);
+  a = {v.x, v.y};
+  b = {v.z, v.w};
+}
+
+// Twiddle and modulation tables of the wave-local pass in LDS, laid out so
+// that the values a lane needs are contiguous (paired 16-byte reads) and the
+// eight rows that the lanes of a wavefront read fall on different banks:
+//   rowT[r TS + k] = w_N^{r k}    (the twiddles of step 1, lane row r = t)
+//   modT[r TS + k] = w_2N^{r + 8k} (the class-1 modulation at point r + 8 k)
+//   colA[q TA + t] = w_N^{q t}    (the twiddles of step 2, row q = q1)
+constexpr int WAVE_TS = 18, WAVE_TA = 10;
+template <typename T>
+struct WaveTabs {
+  const cpx<T>* rowT;
+  const cpx<T>* modT;
+  const cpx<T>* colA;
+};
+
+// v[k] *= r[k] (C = false) or conj(r[k]) (C = true) for k in [K0, L), with r in
+// LDS, 16-byte aligned at even k.  PAIR: two values per 16-byte read, fewer LDS
+// instructions for a few more VALU ones: it pays where the wave-local pass waits
+// on the LDS (one 1024-thread block per CU from n = 96 on: free 128^3, pass B
+// -6 %), not at n = 64, where several blocks share a CU and VALU issue limits
+template <bool C, int K0, int L, bool PAIR, typename T>
+__device__ __forceinline__ void lds_scale(cpx<T>* v, const cpx<T>* r) {
+  static_assert(L % 2 == 0, "even length");
+  if constexpr (!PAIR) {
+#pragma unroll
+    for (int k = K0; k < L; ++k) v[k] = C ? cmulc(v[k], lds_ld(r + k)) : cmul(v[k], lds_ld(r + k));
+    return;
+  }
+  if constexpr (K0 == 1) {
+    const cpx<T> a = lds_ld(r + 1);
+    v[1] = C ? cmulc(v[1], a) : cmul(v[1], a);
+  }
+#pragma unroll
+  for (int k = (K0 == 1 ? 2 : K0); k < L; k += 2) {
+    cpx<T> a, b;
+    lds_ld2(r + k, a, b);
+    v[k] = C ? cmulc(v[k], a) : cmul(v[k], a);
+    v[k + 1] = C ? cmulc(v[k + 1], b) : cmul(v[k + 1], b);
+  }
+}
+
 template <int N>
 constexpr int wave_pitch() {
   int p = 9 * N / 8;
@@ -832,8 +882,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // One y class of the wave-local pass B (CYI = 0 or 1, compile time).  P holds
 // the class-0 output of this lane's column points between the classes.
 template <typename T, int N, int CX, int CY, int CZ, bool EONLY, int CYI>
-__device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T>* __restrict__ tw,
-                                             const cpx<T>* __restrict__ md, cpx<T>* g,
+__device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const WaveTabs<T> tb, cpx<T>* g,
                                              __amdgpu_buffer_rsrc_t grs, const T* kt,
                                              cpx<T> (&P)[N / 8], cpx<T> (&V1)[N / 8],
                                              double& esum) {
@@ -847,6 +896,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
   // phase, and (n > 64) the parked class-0 result during class 1's, so that
   // their latency overlaps the inverse transforms
   constexpr bool EARLY = CY == 2 && !EONLY;
+  constexpr bool WPAIR = N > 64;  // paired table reads (see lds_scale)
   constexpr unsigned KSTRIDE = 8u * CX * N * N * sizeof(cpx<T>);  // slab rows y -> y + 8
 
   // lane coordinates, laundered per class (see opaque)
@@ -869,18 +919,16 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
   {
     cpx<T> v[L1];
 #pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) {
-      const cpx<T> a = (EARLY && CYI == 1) ? V1[k1] : buffer_load_cpx<T>(grs, goff, k1 * KSTRIDE);
-      v[k1] = CYI ? cmul(a, lds_ld(&md[ty + 8 * k1])) : a;
-    }
+    for (int k1 = 0; k1 < L1; ++k1)
+      v[k1] = (EARLY && CYI == 1) ? V1[k1] : buffer_load_cpx<T>(grs, goff, k1 * KSTRIDE);
+    if constexpr (CYI == 1) lds_scale<false, 0, L1, WPAIR>(v, tb.modT + ty * WAVE_TS);
     if constexpr (CYI == 1 && !EONLY && !HOLD) {
       // the class-1 input is in registers: park the class-0 output in the slab
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) *gat(k1) = P[k1];
     }
     Dft<L1, -1, T>::run(v);
-#pragma unroll
-    for (int q1 = 1; q1 < L1; ++q1) v[q1] = cmul(v[q1], lds_ld(&tw[q1 * 8 + ty]));
+    lds_scale<false, 1, L1, WPAIR>(v, tb.rowT + ty * WAVE_TS);
 #pragma unroll
     for (int q1 = 0; q1 < L1; ++q1) Scol[((ty ^ (q1 & 3)) + 8 * q1) * PB] = v[q1];
   }
@@ -964,8 +1012,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
           }
           if (!EONLY) {
             Dft<8, 1, T>::run(w);
-#pragma unroll
-            for (int t = 1; t < 8; ++t) w[t] = cmulc(w[t], lds_ld(&tw[q1 * 8 + t]));
+            lds_scale<true, 1, 8, WPAIR>(w, tb.colA + q1 * WAVE_TA);
 #pragma unroll
             for (int t = 0; t < 8; ++t) Srow[t + 9 * q1] = w[t];
           }
@@ -979,19 +1026,18 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
         u0[k1] = lds_ld(&Srow[tz + 9 * k1]);
-        if constexpr (CZ == 2) u1[k1] = cmul(u0[k1], lds_ld(&md[tz + 8 * k1]));
+        if constexpr (CZ == 2) u1[k1] = u0[k1];
       }
+      if constexpr (CZ == 2) lds_scale<false, 0, L1, WPAIR>(u1, tb.modT + tz * WAVE_TS);
       Dft<L1, -1, T>::run(u0);
-#pragma unroll
-      for (int q1 = 1; q1 < L1; ++q1) u0[q1] = cmul(u0[q1], lds_ld(&tw[q1 * 8 + tz]));
+      lds_scale<false, 1, L1, WPAIR>(u0, tb.rowT + tz * WAVE_TS);
 #pragma unroll
       for (int q1 = 0; q1 < L1; ++q1) Srow[tz + 9 * q1] = u0[q1];
     }
     if constexpr (KPRE) k_load(0, kv0);
     if constexpr (CZ == 2) {
       Dft<L1, -1, T>::run(u1);
-#pragma unroll
-      for (int q1 = 1; q1 < L1; ++q1) u1[q1] = cmul(u1[q1], lds_ld(&tw[q1 * 8 + tz]));
+      lds_scale<false, 1, L1, WPAIR>(u1, tb.rowT + tz * WAVE_TS);
     }
     wave_lds_sync();
     z_mid(0, kv0);
@@ -1016,8 +1062,9 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
         for (int q1 = 0; q1 < L1; ++q1) v[q1] = lds_ld(&Srow[tz + 9 * q1]);
         Dft<L1, 1, T>::run(v);
+        lds_scale<true, 0, L1, WPAIR>(v, tb.modT + tz * WAVE_TS);
 #pragma unroll
-        for (int k1 = 0; k1 < L1; ++k1) acc[k1] = cadd(acc[k1], cmulc(v[k1], lds_ld(&md[tz + 8 * k1])));
+        for (int k1 = 0; k1 < L1; ++k1) acc[k1] = cadd(acc[k1], v[k1]);
       }
     }
     if constexpr (EONLY) {
@@ -1065,8 +1112,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
       const int q1 = ty2 + 8 * j;
       if (q1 < L1) {
         Dft<8, 1, T>::run(w[j]);
-#pragma unroll
-        for (int t = 1; t < 8; ++t) w[j][t] = cmulc(w[j][t], lds_ld(&tw[q1 * 8 + t]));
+        lds_scale<true, 1, 8, WPAIR>(w[j], tb.colA + q1 * WAVE_TA);
 #pragma unroll
         for (int t = 0; t < 8; ++t) Scol2[((t ^ (ty2 & 3)) + 8 * q1) * PB] = w[j][t];
       }
@@ -1079,8 +1125,7 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const cpx<T
 #pragma unroll
     for (int q1 = 0; q1 < L1; ++q1) o[q1] = lds_ld(&Scol2[((ty2 ^ (q1 & 3)) + 8 * q1) * PB]);
     Dft<L1, 1, T>::run(o);
-#pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) o[k1] = CYI ? cmulc(o[k1], lds_ld(&md[ty2 + 8 * k1])) : o[k1];
+    if constexpr (CYI == 1) lds_scale<true, 0, L1, WPAIR>(o, tb.modT + ty2 * WAVE_TS);
     if constexpr (CY == 2 && CYI == 0) {
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) P[k1] = o[k1];
@@ -1110,8 +1155,9 @@ __global__ __launch_bounds__(8 * N) void k_pass_b_wave(cpx<T>* __restrict__ X,
   constexpr bool ANY_PAD = CX == 2 || CY == 2 || CZ == 2;
   static_assert(N % 8 == 0 && L1 <= 16, "line length 8 L1 with L1 <= 16");
   __shared__ cpx<T> S[N * PB];
-  __shared__ cpx<T> tw[L1 * 8];  // tw[q1 8 + t] = w_N^{t q1}: a lane's twiddles are one base plus constants
-  __shared__ cpx<T> md[N];
+  __shared__ __align__(16) cpx<T> rowT[8 * WAVE_TS];
+  __shared__ __align__(16) cpx<T> modT[ANY_PAD ? 8 * WAVE_TS : 2];
+  __shared__ __align__(16) cpx<T> colA[L1 * WAVE_TA];
 
   const int tid = threadIdx.x;
   const int slab = blockIdx.x;  // cx * N + kx
@@ -1122,16 +1168,23 @@ __global__ __launch_bounds__(8 * N) void k_pass_b_wave(cpx<T>* __restrict__ X,
   cpx<T>* g = X + (size_t)ls * CX * N * N * N + slab_base(slab);
   const __amdgpu_buffer_rsrc_t grs = buffer_rsrc(g);
 
-  for (int k = tid; k < N; k += NT) {
-    tw[k] = twg[(k & 7) * (k >> 3)];
-    if (ANY_PAD) md[k] = mdg[k];
+  // every entry a lane reads (k < L1 of a row, t < 8) from the global tables
+  // w_N^k (twg) and w_2N^k (mdg), k < N; 8 L1 = N <= NT threads, one entry of
+  // each table per thread
+  static_assert(8 * L1 <= NT, "one table entry per thread");
+  if (tid < 8 * L1) {
+    const int lo = tid & 7, hi = tid >> 3;  // hi < L1
+    rowT[lo * WAVE_TS + hi] = twg[lo * hi];
+    if (ANY_PAD) modT[lo * WAVE_TS + hi] = mdg[lo + 8 * hi];
+    colA[hi * WAVE_TA + lo] = twg[hi * lo];
   }
   __syncthreads();
 
+  const WaveTabs<T> tb{rowT, modT, colA};
   double esum = 0.0;
   cpx<T> P[L1], V1[L1];
-  wave_y_class<T, N, CX, CY, CZ, EONLY, 0>(S, tw, md, g, grs, kt, P, V1, esum);
-  if constexpr (CY == 2) wave_y_class<T, N, CX, CY, CZ, EONLY, 1>(S, tw, md, g, grs, kt, P, V1, esum);
+  wave_y_class<T, N, CX, CY, CZ, EONLY, 0>(S, tb, g, grs, kt, P, V1, esum);
+  if constexpr (CY == 2) wave_y_class<T, N, CX, CY, CZ, EONLY, 1>(S, tb, g, grs, kt, P, V1, esum);
 
   if constexpr (EONLY) {
     // block reduction of the Parseval sum into this (slot, slab)'s partial

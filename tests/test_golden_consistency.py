@@ -2,7 +2,8 @@
 
 tests/golden/*_oracle.npz were written by make_oracle_golden.py (oracle only);
 re-solving one stored pair per file pins the generator, the oracle and the
-files to each other.
+files to each other (the 256-orbital 128^3 system takes about 30 s and 4.3 GB
+to regenerate).
 """
 import glob
 import os
@@ -26,8 +27,6 @@ def _system(name):
 @pytest.mark.parametrize("path", FILES, ids=lambda p: os.path.basename(p).replace("_oracle.npz", ""))
 def test_one_pair_recomputes(path):
     name = os.path.basename(path).replace("_oracle.npz", "")
-    if name == "free128_n256":
-        pytest.skip("4 GB input; covered by the GPU full-size test")
     g = dict(np.load(path))
     s = _system(name)
     assert int(g["n"]) == s.n and int(g["n_orb"]) == s.n_orb

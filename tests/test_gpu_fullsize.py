@@ -75,8 +75,11 @@ def check(name, precision):
     assert r["E"] == pytest.approx(-0.5 * float(f @ P @ f), rel=1e-12)
     assert r["E_from_kpsi"] == pytest.approx(r["E"], rel=max(tol, 1e-12))
     if "E" in g:
-        assert abs(r["E"] - float(g["E"])) / s.n_orb < (1e-6 if precision == "fp32" else 1e-12 * abs(float(g["E"])))
-        assert np.max(np.abs(P - g["pair_e"])) <= tol * scale
+        dE = abs(r["E"] - float(g["E"])) / s.n_orb
+        dP = np.max(np.abs(P - g["pair_e"])) / scale
+        say(f"  |dE_x|/N = {dE:.3e} Ha, max |d e_ij| / max e_ij = {dP:.3e}")
+        assert dE < (1e-6 if precision == "fp32" else 1e-12 * abs(float(g["E"])))
+        assert dP <= tol
     if "pairs" in g:
         got = np.array([P[i, j] for i, j in g["pairs"]])
         assert np.max(np.abs(got - g["pair_energies"])) <= tol * scale
@@ -132,7 +135,8 @@ def test_free128_n256_fp32_against_fp64_plain():
     r64 = evaluate(s, "fp64_plain")
     k64 = r64.pop("kpsi")[rows].cpu().numpy()
     dE = abs(r32["E"] - r64["E"]) / s.n_orb
-    say(f"  |dE_x|/N = {dE:.3e} Ha, E_x = {r64['E']:.12f}")
+    dP = np.max(np.abs(r32["pair_e"] - r64["pair_e"])) / np.max(np.abs(r64["pair_e"]))
+    say(f"  |dE_x|/N = {dE:.3e} Ha, max |d e_ij| / max e_ij = {dP:.3e}, E_x = {r64['E']:.12f}")
     assert dE < 1e-6
     scale = float(np.max(np.abs(r64["pair_e"])))
     assert np.max(np.abs(r32["pair_e"] - r64["pair_e"])) <= 1e-5 * scale
