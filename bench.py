@@ -305,43 +305,60 @@ def cpu_baseline(sysm, n_sample: int) -> dict:
 
 
 def bench_batch(a, dev) -> int:
-    """Sixteen uneven isolated systems in one captured HIP graph (FP32 path),
-    with the plans' default tunings, or tuned per grid class by
-    exx_batch_autotune first when --batch-tune-ms is given."""
+    """Batches of uneven isolated systems in one captured HIP graph (FP32 path):
+    16 systems of n in {48..112} (batch16_free) or 48 small ones of n in
+    {32, 48} (batch48_small); with the plans' default tunings, or tuned per grid
+    class by exx_batch_autotune first when --batch-tune-ms is given; with
+    --merge, systems on one grid share their launches (EXX_BATCH_MERGE), and the
+    line also reports the unmerged batch measured the same way."""
     import torch
 
     import paper_1712_07973_amd as exx
-    from exx_inputs import batch_recipes, make_system, pair_count
-    systems = [make_system(r) for r in batch_recipes()]
+    from exx_inputs import batch_recipes, make_system, pair_count, small_batch_recipes
+    small = a.workload == "batch48_small"
+    systems = [make_system(r) for r in (small_batch_recipes() if small else batch_recipes())]
     grids = [exx.Grid(n=s.n, h=s.h, bc=s.bc, R=s.R) for s in systems]
     psis = [torch.from_numpy(s.psi).to(dev) for s in systems]
     occs = [torch.from_numpy(s.occ).to(dev) for s in systems]
     pairs = sum(pair_count(s.n_orb) for s in systems)
-    b = exx.Batch(grids, [s.n_orb for s in systems], "fp32", use_graph=True)
-    t0 = time.perf_counter()
-    tunings = b.autotune(psis, occs, budget_ms=a.batch_tune_ms) if a.batch_tune_ms > 0 else b.tunings()
-    tune_s = time.perf_counter() - t0
-    outs = None
-    for _ in range(max(1, a.warmup)):
-        outs = b.compute(psis, occs, outputs=outs)
-    torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(a.steps):
-        b.compute(psis, occs, outputs=outs)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / a.steps
+
+    def run(merge):
+        b = exx.Batch(grids, [s.n_orb for s in systems], "fp32", use_graph=True, merge=merge)
+        t0 = time.perf_counter()
+        tun = (b.autotune(psis, occs, budget_ms=a.batch_tune_ms) if a.batch_tune_ms > 0 and not merge
+               else b.tunings())
+        tune_s = time.perf_counter() - t0
+        outs = None
+        for _ in range(max(1, a.warmup)):
+            outs = b.compute(psis, occs, outputs=outs)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(a.steps):
+            b.compute(psis, occs, outputs=outs)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        E = [float(o[0].item()) for o in outs]
+        del b, outs
+        torch.cuda.empty_cache()
+        return e0.elapsed_time(e1) / a.steps, tun, tune_s, E
+
+    ms, tunings, tune_s, E_x = run(a.merge)
+    other = run(False) if a.merge else None
     model = sum(sum(model_a_bytes(s.n, CLASSES[s.bc], pair_count(s.n_orb)).values()) for s in systems)
     gbs = model / (ms * 1e-3) / 1e9
     out = {"metric": METRIC, "value": round(pairs / (ms * 1e-3), 1), "unit": "pair-solves/s",
            "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": "16 isolated systems, n in {48..112} padded to 2n, N in [16,96], "
-                                  "one captured HIP graph per evaluation",
+           "config": {"workload": (("48 isolated systems, n in {32, 48} padded to 2n, N in [4,16]"
+                                    if small else
+                                    "16 isolated systems, n in {48..112} padded to 2n, N in [16,96]")
+                                   + ", one captured HIP graph per evaluation"
+                                   + (", systems on one grid sharing launches" if a.merge else "")),
+                      "preset": a.workload, "merge": bool(a.merge),
                       "pairs": pairs, "systems": [[s.n, s.n_orb] for s in systems],
                       "tunings": tunings, "autotune_s": round(tune_s, 1)},
            "roofline": {"bound": "hbm", "kernel": "whole evaluation (every pass of every system)",
@@ -350,9 +367,10 @@ def bench_batch(a, dev) -> int:
                         "bytes_per_launch": int(model),
                         "bytes_model": "two spectrum round trips, 4 B per real pair per complex "
                                        "point, cx cy n^3 points (z pruned)"},
-           "E_x": [float(o[0].item()) for o in outs]}
-    del b
-    torch.cuda.empty_cache()
+           "E_x": E_x}
+    if other is not None:
+        out["unmerged"] = {"value": round(pairs / (other[0] * 1e-3), 1), "ms_per_step": round(other[0], 3),
+                           "E_x_equal": other[3] == E_x}
     if not a.no_baselines:
         # FP64 leg: the plain path on the systems of n <= 64 (a labelled subset),
         # one plan per system called in turn, with the FP32 path on the same
@@ -422,6 +440,8 @@ def main(argv=None) -> int:
     ap.add_argument("--radius", default="box", choices=["box", "diagonal"],
                     help="free-BC truncation radius: box (R = L = n h, the default) or diagonal "
                          "(R = sqrt(3) L; the 2n-padded grid then aliases periodic images)")
+    ap.add_argument("--merge", action="store_true",
+                    help="batch workloads: systems on one grid share their launches")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device-to-device 3 times (calibrates memory counters)")
     a = ap.parse_args(argv)
@@ -450,7 +470,7 @@ def main(argv=None) -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_per_launch": src.numel() * 4, "launches": 3}))
         return 0
-    if a.workload == "batch16_free":
+    if a.workload in ("batch16_free", "batch48_small"):
         return bench_batch(a, dev)
     sysm = system(a.workload)
     N, n = sysm.n_orb, sysm.n

@@ -53,6 +53,19 @@ def recipe(name: str) -> OrbitalRecipe:
 SINGLE = ("periodic32_n8", "free64_n32", "periodic96_n128", "free128_n256", "surface64_n32",
           "wire64_n32", "free64_n32_complex")
 BATCH = "batch16_free"
+BATCH_SMALL = "batch48_small"
+
+
+def small_batch_recipes(n_systems: int = 48, seed: int = 1009):
+    """Many small isolated systems: n in {32, 48}, N in [4, 16]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_systems):
+        n = int(rng.choice([32, 48]))
+        N = int(rng.integers(4, 17))
+        out.append(OrbitalRecipe(n=n, h=H, n_orb=N, n_gauss=4, sigma=(0.6, 1.5),
+                                 centres="middle", bc=FREE, seed=1100 + s))
+    return out
 
 
 def batch_recipes(n_systems: int = 16, seed: int = 1005):

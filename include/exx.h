@@ -254,6 +254,7 @@ typedef struct exx_batch exx_batch;
 /* Flags of exx_batch_create. */
 #define EXX_BATCH_GRAPH 1u   /* capture the evaluation into a HIP graph and replay it */
 #define EXX_BATCH_COMPLEX 2u /* every system has complex orbitals (as EXX_PLAN_COMPLEX) */
+#define EXX_BATCH_MERGE 4u   /* shared launches per grid class (below) */
 
 /* A batch of n_systems independent systems (any mix of supported grids and
  * orbital counts, one precision, all real or all complex orbitals; e.g. the
@@ -264,7 +265,18 @@ typedef struct exx_batch exx_batch;
  * whole evaluation is captured into one HIP graph on the first
  * exx_batch_compute and replayed afterwards, one graph launch per call (the
  * system pointers, mode, flags, workspace and stream must then stay the same;
- * a change recaptures).  Unknown flag bits give EXX_ERR_INVALID_ARG. */
+ * a change recaptures).  Unknown flag bits give EXX_ERR_INVALID_ARG.
+ *
+ * EXX_BATCH_MERGE (FP32 only): systems on the same grid (size, spacing,
+ * boundary, kernel, radius) form a class of up to 32 systems that share
+ * launches: their pair schedules are merged (the round-robin rounds of tile
+ * pairs of every member, round by round, Sec. 2.1), so one pass-A and one
+ * pass-B launch cover a chunk of all members' slots and one pass-C launch a
+ * round of all members' tile pairs; the classes run on the side streams.
+ * Results equal the unmerged batch's bit for bit.  A merged batch evaluates
+ * EXX_MODE_KPSI and EXX_MODE_ENERGY_KPSI without pair energies (pair_e NULL);
+ * other calls, and exx_batch_autotune, give EXX_ERR_INVALID_ARG.  It sizes its
+ * workspace per class rather than per system. */
 int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, int n_systems,
                      int precision, unsigned flags);
 void exx_batch_destroy(exx_batch* batch);

@@ -18,7 +18,7 @@ PREC_FP32, PREC_FP64_PLAIN, PREC_FP64_FUSED = 0, 1, 2
 MODE_ENERGY, MODE_KPSI, MODE_ENERGY_KPSI = 1, 2, 3
 FLAG_ACCUMULATE = 1
 PLAN_COMPLEX = 1
-BATCH_GRAPH, BATCH_COMPLEX = 1, 2
+BATCH_GRAPH, BATCH_COMPLEX, BATCH_MERGE = 1, 2, 4
 
 ERRORS = {
     0: "EXX_OK", -1: "EXX_ERR_INVALID_ARG", -2: "EXX_ERR_UNSUPPORTED_SIZE", -3: "EXX_ERR_CAPACITY",

@@ -15,19 +15,22 @@ class Batch:
     With ``use_graph`` the first call captures the whole evaluation into a HIP
     graph and later calls with the same tensors replay it.  With
     ``complex_orbitals`` every system's psi is complex128.  The two spin
-    channels of a spin-polarized system are a batch of two systems.
+    channels of a spin-polarized system are a batch of two systems.  With
+    ``merge`` (FP32) systems on one grid share their launches (EXX_BATCH_MERGE:
+    "kpsi" and "energy_kpsi" modes).
     """
 
     def __init__(self, grids: list[Grid], n_orb: list[int], precision: str = "fp32",
                  use_graph: bool = True, device: torch.device | None = None,
-                 complex_orbitals: bool = False):
+                 complex_orbitals: bool = False, merge: bool = False):
         if len(grids) != len(n_orb) or not grids:
             raise ValueError("grids and n_orb must be non-empty lists of equal length")
         self.grids = list(grids)
         self.n_orb = [int(x) for x in n_orb]
         self.device = device or torch.device("cuda", torch.cuda.current_device())
         self.dtype = torch.complex128 if complex_orbitals else torch.float64
-        flags = (L.BATCH_GRAPH if use_graph else 0) | (L.BATCH_COMPLEX if complex_orbitals else 0)
+        flags = ((L.BATCH_GRAPH if use_graph else 0) | (L.BATCH_COMPLEX if complex_orbitals else 0)
+                 | (L.BATCH_MERGE if merge else 0))
         arr = (L.ExxGrid * len(grids))(*[g.to_c() for g in grids])
         na = (C.c_int * len(grids))(*self.n_orb)
         h = C.c_void_p()

@@ -506,6 +506,122 @@ int validate_grid(const exx_grid* g, int precision) {
 
 }  // namespace
 
+int exx::build_merged_class(const std::vector<exx_plan*>& plans, const std::vector<int>& n_orb,
+                            MergedClass& mc) {
+  if (mc.members.empty() || (int)mc.members.size() > kMaxMergedSystems)
+    return fail(EXX_ERR_INVALID_ARG, "a merged class holds 1 to 32 systems");
+  exx_plan* p = plans[mc.members[0]];
+  if (!is_fp32(p)) return fail(EXX_ERR_INVALID_ARG, "merged launches need the FP32 path");
+  std::vector<const Schedule*> parts;
+  for (int s : mc.members) {
+    Schedule* sc = nullptr;
+    if (int rc = get_schedule(plans[s], n_orb[s], &sc, true)) return rc;
+    parts.push_back(sc);
+  }
+  merge_schedules(parts, p->tuning.batch_slots, mc.sched, mc.orb_base, mc.tile_base);
+  Schedule& s = mc.sched;
+  EXX_HIP(hipSetDevice(p->device));
+  EXX_HIP(hipMalloc((void**)&s.d_slots, std::max<size_t>(1, s.slots.size()) * sizeof(Slot)));
+  EXX_HIP(hipMemcpy(s.d_slots, s.slots.data(), s.slots.size() * sizeof(Slot), hipMemcpyHostToDevice));
+  EXX_HIP(hipMalloc((void**)&s.d_tiles, std::max<size_t>(1, s.tiles.size()) * sizeof(TilePair)));
+  EXX_HIP(hipMemcpy(s.d_tiles, s.tiles.data(), s.tiles.size() * sizeof(TilePair), hipMemcpyHostToDevice));
+  // class workspace: FP32 orbitals of every member end to end, per-tile energy
+  // partials and sums, the spectrum of the largest chunk, the split pass B scratch
+  const size_t orbs = (size_t)s.n_orb * p->n * p->n * p->n * (p->cplx ? 2 : 1);
+  size_t off = 0;
+  mc.psi32 = off;
+  off += align_up(orbs * sizeof(float), 256);
+  mc.e_part = off;
+  off += align_up(s.tiles.size() * (size_t)energy_parts(p->n) * sizeof(double), 256);
+  mc.e_slot = off;
+  off += align_up(s.tiles.size() * sizeof(double), 256);
+  mc.X = off;
+  off += align_up((size_t)cap_slots(p, s) * slot_bytes(p), 256);
+  mc.Y = off;
+  mc.split_slots = 0;
+  if (uses_split(p)) {
+    const size_t budget = (size_t)512 << 20;
+    mc.split_slots = (int)std::max<size_t>(1, std::min<size_t>(cap_slots(p, s), budget / split_slot_bytes(p)));
+    off += align_up((size_t)mc.split_slots * split_slot_bytes(p), 256);
+  }
+  mc.ws_bytes = off;
+  return EXX_OK;
+}
+
+void exx::free_merged_class(MergedClass& mc) {
+  if (mc.sched.d_slots) (void)hipFree(mc.sched.d_slots);
+  if (mc.sched.d_tiles) (void)hipFree(mc.sched.d_tiles);
+  mc.sched.d_slots = nullptr;
+  mc.sched.d_tiles = nullptr;
+}
+
+int exx::run_merged_class(const std::vector<exx_plan*>& plans, const MergedClass& mc,
+                          const exx_system* sys, int mode, unsigned flags, char* ws, hipStream_t st) {
+  exx_plan* p = plans[mc.members[0]];
+  const Schedule& s = mc.sched;
+  const bool want_e = (mode & EXX_MODE_ENERGY) != 0;
+  const size_t n3 = (size_t)p->n * p->n * p->n * (p->cplx ? 2 : 1);
+  char* base = ws + mc.ws_off;
+  float* psi32 = reinterpret_cast<float*>(base + mc.psi32);
+  double* e_part = reinterpret_cast<double*>(base + mc.e_part);
+  double* e_slot = reinterpret_cast<double*>(base + mc.e_slot);
+  char* X = base + mc.X;
+  const size_t sb = slot_bytes(p);
+  const int kparts = energy_parts(p->n);
+  const int k_mode = (flags & EXX_FLAG_ACCUMULATE) ? 1 : 2;
+  Launch L{p->n, p->ncls, p->cy, p->cz, p->h3, st, p->cplx ? 1 : 0, p->swap_yz ? 1 : 0};
+  // every member's orbitals into the class's FP32 copy (one launch), and its
+  // outputs addressed with merged orbital indices (pointers offset back by its
+  // first merged orbital)
+  SysTab tab;
+  MemberTab mt;
+  tab.n = mt.n = (int)mc.members.size();
+  size_t max_count = 0;
+  for (size_t k = 0; k < mc.members.size(); ++k) {
+    const exx_system& y = sys[mc.members[k]];
+    const int N = (k + 1 < mc.members.size() ? mc.orb_base[k + 1] : s.n_orb) - mc.orb_base[k];
+    mt.psi[k] = y.psi;
+    mt.count[k] = (size_t)N * n3;
+    mt.dst_off[k] = (size_t)mc.orb_base[k] * n3;
+    mt.row0[k] = mc.tile_base[k];
+    mt.ex_out[k] = y.ex_out;
+    max_count = std::max(max_count, mt.count[k]);
+    tab.kpsi[k] = reinterpret_cast<double*>(reinterpret_cast<uintptr_t>(y.kpsi) -
+                                            (uintptr_t)mc.orb_base[k] * n3 * sizeof(double));
+    tab.occ[k] = reinterpret_cast<const double*>(reinterpret_cast<uintptr_t>(y.occ) -
+                                                 (uintptr_t)mc.orb_base[k] * sizeof(double));
+  }
+  mt.row0[mt.n] = (int)s.tiles.size();
+  EXX_HIP(launch_convert_members(mt, psi32, max_count, st));
+  for (const auto& c : s.chunks) {
+    const int ns = c.s1 - c.s0;
+    EXX_HIP(launch_pass_a<float>(L, psi32, X, s.d_slots, c.s0, ns, nullptr, false, p->tables));
+    if (mc.split_slots == 0) {
+      EXX_HIP(launch_pass_b<float>(L, X, ns, false, e_part, c.s0, p->tables, p->tuning.slab_threads,
+                                   p->tuning.slab_form));
+    } else {
+      for (int a = 0; a < ns; a += mc.split_slots) {
+        const int k = std::min(mc.split_slots, ns - a);
+        EXX_HIP(launch_pass_b_split<float>(L, X + (size_t)a * sb, base + mc.Y, k, false, e_part,
+                                           c.s0 + a, p->tables));
+      }
+    }
+    for (int g = c.seg0; g < c.seg1; ++g) {
+      const auto& sg = s.segments[g];
+      EXX_HIP(launch_pass_c<float>(L, X, psi32, nullptr, s.d_slots, s.d_tiles, sg.t0, sg.t1 - sg.t0,
+                                   c.s0, nullptr, e_part, k_mode, want_e, false, s.tile, p->tables,
+                                   &tab));
+    }
+  }
+  if (want_e) {
+    // every tile pair's weighted partials, then per member the sum of its rows,
+    // each in the fixed order of the unmerged evaluation
+    EXX_HIP(launch_slot_reduce(e_part, kparts, p->n * p->n / 16, (int)s.tiles.size(), e_slot, st));
+    EXX_HIP(launch_finalize_members(mt, e_slot, p->h3, st));
+  }
+  return EXX_OK;
+}
+
 int exx::compute_impl(exx_plan* p, const double* psi, const double* occ, int n_orb, int mode,
                       unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
                       size_t ws_bytes, void* stream, bool may_allocate) {

@@ -37,6 +37,8 @@ struct exx_batch {
   std::vector<hipStream_t> side;  // default-priority, non-blocking
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
+  bool merge = false;                    // EXX_BATCH_MERGE
+  std::vector<exx::MergedClass> classes;  // with merge: every system in one class
 };
 
 namespace {
@@ -61,6 +63,12 @@ bool same_systems(const std::vector<exx_system>& a, const exx_system* b, size_t 
   return true;
 }
 
+// Two grids that give the same kernels and kernel table.
+bool same_grid(const exx_grid& a, const exx_grid& c) {
+  return a.nx == c.nx && a.ny == c.ny && a.nz == c.nz && a.hx == c.hx && a.hy == c.hy &&
+         a.hz == c.hz && a.bc == c.bc && a.kernel == c.kernel && a.R == c.R && a.omega == c.omega;
+}
+
 }  // namespace
 
 extern "C" {
@@ -69,8 +77,10 @@ int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, i
                      int precision, unsigned flags) {
   if (!out || !grids || !n_orb || n_systems <= 0)
     return record_error(EXX_ERR_INVALID_ARG, "out, grids and n_orb are required and n_systems > 0");
-  if ((flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_COMPLEX)) != 0)
+  if ((flags & ~(EXX_BATCH_GRAPH | EXX_BATCH_COMPLEX | EXX_BATCH_MERGE)) != 0)
     return record_error(EXX_ERR_INVALID_ARG, "unknown batch flags");
+  if ((flags & EXX_BATCH_MERGE) && precision != EXX_PREC_FP32)
+    return record_error(EXX_ERR_INVALID_ARG, "EXX_BATCH_MERGE needs the FP32 path");
   *out = nullptr;
   exx_batch* b = new (std::nothrow) exx_batch();
   if (!b) return record_error(EXX_ERR_INTERNAL, "out of host memory");
@@ -94,6 +104,33 @@ int exx_batch_create(exx_batch** out, const exx_grid* grids, const int* n_orb, i
     off += (bytes + 255) / 256 * 256;
   }
   b->ws_total = off;
+  if (flags & EXX_BATCH_MERGE) {
+    // classes of systems on one grid (at most kMaxMergedSystems each); the
+    // workspace becomes one region per class
+    b->merge = true;
+    std::vector<int> cls(n_systems, -1);
+    for (int s = 0; s < n_systems; ++s) {
+      if (cls[s] >= 0) continue;
+      exx::MergedClass mc;
+      for (int c = s; c < n_systems && (int)mc.members.size() < exx::kMaxMergedSystems; ++c)
+        if (cls[c] < 0 && same_grid(grids[s], grids[c])) {
+          cls[c] = (int)b->classes.size();
+          mc.members.push_back(c);
+        }
+      b->classes.push_back(mc);
+    }
+    off = 0;
+    for (auto& mc : b->classes) {
+      int rc = exx::build_merged_class(b->plans, b->n_orb, mc);
+      if (rc != EXX_OK) {
+        exx_batch_destroy(b);
+        return rc;
+      }
+      mc.ws_off = off;
+      off += (mc.ws_bytes + 255) / 256 * 256;
+    }
+    b->ws_total = off;
+  }
   const int ns = std::min<int>(kSideStreams, n_systems);
   if (hipError_t e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming); e != hipSuccess) {
     exx_batch_destroy(b);
@@ -120,6 +157,7 @@ void exx_batch_destroy(exx_batch* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& mc : b->classes) exx::free_merged_class(mc);
   for (auto* p : b->plans) exx_plan_destroy(p);
   for (auto st : b->side) (void)hipStreamDestroy(st);
   for (auto ev : b->join) (void)hipEventDestroy(ev);
@@ -139,6 +177,18 @@ static int batch_issue(exx_batch* b, const exx_system* sys, int mode, unsigned f
                        hipStream_t st) {
   EXX_BATCH_HIP(hipEventRecord(b->fork, st));
   for (auto side : b->side) EXX_BATCH_HIP(hipStreamWaitEvent(side, b->fork, 0));
+  if (b->merge) {
+    // one merged class per side stream in turn
+    int rc = EXX_OK;
+    for (size_t k = 0; k < b->classes.size() && rc == EXX_OK; ++k)
+      rc = exx::run_merged_class(b->plans, b->classes[k], sys, mode, flags, ws,
+                                 b->side[k % b->side.size()]);
+    for (size_t k = 0; k < b->side.size(); ++k) {
+      EXX_BATCH_HIP(hipEventRecord(b->join[k], b->side[k]));
+      EXX_BATCH_HIP(hipStreamWaitEvent(st, b->join[k], 0));
+    }
+    return rc;
+  }
   std::vector<size_t> order(b->plans.size());
   for (size_t s = 0; s < order.size(); ++s) order[s] = s;
   auto work = [&](size_t s) {
@@ -169,6 +219,16 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
     return record_error(EXX_ERR_WORKSPACE, "workspace smaller than exx_batch_workspace_bytes(): need " +
                                                std::to_string(b->ws_total));
   if (((uintptr_t)ws % 256) != 0) return record_error(EXX_ERR_ALIGNMENT, "workspace must be 256-byte aligned");
+  if (b->merge) {
+    if (mode != EXX_MODE_KPSI && mode != EXX_MODE_ENERGY_KPSI)
+      return record_error(EXX_ERR_INVALID_ARG, "a merged batch evaluates the KPSI and ENERGY_KPSI modes");
+    if ((flags & ~EXX_FLAG_ACCUMULATE) != 0) return record_error(EXX_ERR_INVALID_ARG, "unknown flags");
+    for (size_t s = 0; s < b->plans.size(); ++s) {
+      if (sys[s].pair_e) return record_error(EXX_ERR_INVALID_ARG, "a merged batch gives no pair energies");
+      if (!sys[s].psi || !sys[s].occ || !sys[s].kpsi || ((mode & EXX_MODE_ENERGY) && !sys[s].ex_out))
+        return record_error(EXX_ERR_INVALID_ARG, "psi, occ, kpsi (and ex_out for energies) are required");
+    }
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* wsc = static_cast<char*>(ws);
   if (!b->use_graph) return batch_issue(b, sys, mode, flags, wsc, st);
@@ -214,18 +274,16 @@ int exx_batch_compute(exx_batch* b, const exx_system* sys, int mode, unsigned fl
 int exx_batch_autotune(exx_batch* b, const exx_system* sys, void* ws, size_t ws_bytes,
                        void* stream, int budget_ms, const char* cache_path) {
   if (!b || !sys) return record_error(EXX_ERR_INVALID_ARG, "batch or systems is NULL");
+  if (b->merge) return record_error(EXX_ERR_INVALID_ARG, "a merged batch is not autotuned");
   if (!ws || ws_bytes < b->ws_total)
     return record_error(EXX_ERR_WORKSPACE, "workspace smaller than exx_batch_workspace_bytes(): need " +
                                                std::to_string(b->ws_total));
   const size_t n = b->plans.size();
   // classes: systems on the same grid (same kernels and kernel table); each is
   // tuned on its member with the most orbitals
-  auto same_grid = [&](size_t a, size_t c) {
-    const exx_grid& ga = b->plans[a]->grid;
-    const exx_grid& gc = b->plans[c]->grid;
-    return ga.nx == gc.nx && ga.ny == gc.ny && ga.nz == gc.nz && ga.hx == gc.hx && ga.hy == gc.hy &&
-           ga.hz == gc.hz && ga.bc == gc.bc && ga.kernel == gc.kernel && ga.R == gc.R &&
-           ga.omega == gc.omega && b->plans[a]->precision == b->plans[c]->precision;
+  auto same_class = [&](size_t a, size_t c) {
+    return same_grid(b->plans[a]->grid, b->plans[c]->grid) &&
+           b->plans[a]->precision == b->plans[c]->precision;
   };
   std::vector<int> cls(n, -1);
   std::vector<size_t> rep;
@@ -234,7 +292,7 @@ int exx_batch_autotune(exx_batch* b, const exx_system* sys, void* ws, size_t ws_
     cls[s] = (int)rep.size();
     size_t best = s;
     for (size_t c = s + 1; c < n; ++c)
-      if (cls[c] < 0 && same_grid(s, c)) {
+      if (cls[c] < 0 && same_class(s, c)) {
         cls[c] = cls[s];
         if (b->n_orb[c] > b->n_orb[best]) best = c;
       }

@@ -96,6 +96,24 @@ hipError_t launch_convert(const double* psi, float* psi32, size_t count, hipStre
   return hipGetLastError();
 }
 
+// FP32 copies of every member of a merged class (blockIdx.y = member)
+__global__ void k_convert_members(const MemberTab m, float* __restrict__ b) {
+  const int k = blockIdx.y;
+  const double* __restrict__ a = m.psi[k];
+  float* __restrict__ d = b + m.dst_off[k];
+  const size_t n = m.count[k];
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) d[i] = (float)a[i];
+}
+
+hipError_t launch_convert_members(const MemberTab& m, float* psi32, size_t max_count, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<size_t>((max_count + 255) / 256, 65536);
+  if (blocks == 0 || m.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert_members, dim3(blocks, m.n), dim3(256), 0, s, m, psi32);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero(double* p, size_t count, hipStream_t s) {
   unsigned blocks = (unsigned)std::min<size_t>((count + 255) / 256, 65536);
   if (blocks == 0) return hipSuccess;
@@ -1510,14 +1528,16 @@ __global__ __launch_bounds__(NT) void k_pass_b3(cpx<T>* __restrict__ X, const cp
 // pairs (the first round, which holds every orbital once) store their row
 // sums, so K psi needs no clearing beforehand.
 // ---------------------------------------------------------------------------
-// Threads per owned row segment: above n = 64, where L1 = n / 16 is even, two
-// threads share each (row, t) segment of L1 points, each reducing half of them,
-// so that a pair tile of 8 orbitals fits the registers (its K psi sums are
-// (tile + 1) L1 / HP FP64 values per thread) and K psi is read and written half
-// as often as with a tile of 4.
+// Threads per owned row segment: from n = 96 on two threads share each (row, t)
+// segment of L1 = n / 16 points, the first reducing ceil(L1 / 2) of them and the
+// second the rest, so that a pair tile of 8 orbitals fits the registers (its K
+// psi sums are (tile + 1) ceil(L1 / HP) FP64 values per thread) and K psi is
+// read and written half as often as with a tile of 4.  At n = 80 the one-thread
+// form with a tile of 4 is faster (two 256-thread blocks per CU against one
+// 512-thread block: 4.6 against 6.2 ms of pass C for 67 orbitals).
 template <typename T, int N>
 constexpr int pass_c_halves() {
-  return (sizeof(T) == 4 && N > 64 && (N / 16) % 2 == 0) ? 2 : 1;
+  return (sizeof(T) == 4 && N >= 96) ? 2 : 1;
 }
 
 // pair-tile edge of the variant with HP threads per segment: the K psi register
@@ -1561,7 +1581,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
                                                int want_e, int pair_out,
                                                const cpx<T>* __restrict__ twg,
                                                const cpx<T>* __restrict__ mdg, int kparts,
-                                               int swap_yz) {
+                                               int swap_yz, const SysTab systab) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
@@ -1570,9 +1590,9 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   constexpr int MAXS = TM * HB;               // slots per tile pair
   constexpr int NW = NT / 64;
   constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
-  constexpr int LP = L1 / HP;                 // points per thread
+  constexpr int LP = (L1 + HP - 1) / HP;      // points per thread (the last half may own one less)
+  constexpr bool EVEN = L1 % HP == 0;
   static_assert(ZB * L2 * HP == NT, "HP point-owner threads per (row, t)");
-  static_assert(L1 % HP == 0, "halves of equal size");
   static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
   // Spectrum rows of the current slot.  One buffer suffices: the store of
   // slot k+1 follows the second barrier of slot k, after every read of xs.
@@ -1593,12 +1613,20 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   const int y = blockIdx.x / (N / ZB);
   const int z0 = (blockIdx.x % (N / ZB)) * ZB;
   const TilePair tp = tiles[t0 + blockIdx.y];
+  // this tile pair's system (merged batch schedules) or the launch's own buffers
+  const double* __restrict__ occ_s = systab.n ? systab.occ[tp.sys] : occ;
+  double* __restrict__ kpsi_s = systab.n ? systab.kpsi[tp.sys] : kpsi;
   const size_t M3 = (size_t)N * N * N;
   // owner of (row zi_own, t_own), points x = t_own + 16 k1 for k1 in [k0, k0 + LP)
+  // clipped to L1 (a half's threads are whole wavefronts, so the clipped point is
+  // skipped without divergence; it is read at the last valid point and
+  // contributes zeros)
   // (threads of one half are contiguous, so K psi updates stay 128-byte runs)
   const int h_own = tid / (ZB * L2), rt = tid % (ZB * L2);
   const int t_own = rt % L2, zi_own = rt / L2;
   const int k0 = h_own * LP;
+  auto kok = [&](int k1) { return EVEN || k0 + k1 < L1; };
+  auto kcl = [&](int k1) { return EVEN ? k0 + k1 : min(k0 + k1, L1 - 1); };
   const unsigned hmask = opaque(h_own ? ~0u : 0u);  // second half of a segment
   // offset of the owned row (swap_yz: spectrum (y, z) = grid (z, y))
   const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
@@ -1610,8 +1638,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   }
   for (int k = tid; k < TM * HB; k += NT) smap[k / HB][k % HB] = -1;
   for (int k = tid; k < TM; k += NT) {
-    fI[k] = k < tp.nI ? occ[tp.I0 + k] : 0.0;
-    fJ[k] = k < tp.nJ ? occ[tp.J0 + k] : 0.0;
+    fI[k] = k < tp.nI ? occ_s[tp.I0 + k] : 0.0;
+    fJ[k] = k < tp.nJ ? occ_s[tp.J0 + k] : 0.0;
   }
   __syncthreads();
   for (int k = tid; k < ns; k += NT) {
@@ -1647,7 +1675,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     if (b >= tp.nJ) continue;
     const T* po = psi + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
-    for (int k1 = 0; k1 < LP; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * (k0 + k1)];
+    for (int k1 = 0; k1 < LP; ++k1) pJs[b][k1 * NT + tid] = kok(k1) ? po[t_own + L2 * kcl(k1)] : T(0);
   }
   __syncthreads();
   if (ns > 0) fetch(0);
@@ -1662,7 +1690,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 #pragma unroll
       for (int k1 = 0; k1 < LP; ++k1) {
         accI[k1] = 0.0;
-        pI[k1] = po[t_own + L2 * (k0 + k1)];
+        pI[k1] = kok(k1) ? po[t_own + L2 * kcl(k1)] : T(0);
       }
     }
     const double fa = fI[a];
@@ -1707,7 +1735,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 #pragma unroll
         for (int k1 = 0; k1 < LP; ++k1)
           V[k1] = HP == 1 ? v[k1]
-                          : cpx<T>{pick(hmask, v[k1].x, v[LP % L1 + k1].x), pick(hmask, v[k1].y, v[LP % L1 + k1].y)};
+                          : cpx<T>{pick(hmask, v[k1].x, v[min(LP % L1 + k1, L1 - 1)].x),
+                                   pick(hmask, v[k1].y, v[min(LP % L1 + k1, L1 - 1)].y)};
         if (NCLS == 2) {
 #pragma unroll
           for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
@@ -1715,9 +1744,9 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 #pragma unroll
           for (int k1 = 0; k1 < LP; ++k1) {
             const cpx<T> w = HP == 1 ? v[k1]
-                                     : cpx<T>{pick(hmask, v[k1].x, v[LP % L1 + k1].x),
-                                              pick(hmask, v[k1].y, v[LP % L1 + k1].y)};
-            V[k1] = cadd(V[k1], cmulc(w, md[t_own + L2 * (k0 + k1)]));
+                                     : cpx<T>{pick(hmask, v[k1].x, v[min(LP % L1 + k1, L1 - 1)].x),
+                                              pick(hmask, v[k1].y, v[min(LP % L1 + k1, L1 - 1)].y)};
+            V[k1] = cadd(V[k1], cmulc(w, md[t_own + L2 * kcl(k1)]));
           }
         }
       }
@@ -1759,7 +1788,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       ++k;
     }
     if (want_k) {
-      double* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+      double* ko = kpsi_s + (size_t)(tp.I0 + a) * M3 + row;
       if (tp.diag) {
         // on a diagonal tile orbital a's column sums (from rows a' < a) are
         // complete here: one write carries both
@@ -1771,10 +1800,12 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       }
       if (want_k == 2 && tp.diag) {  // first write of this orbital row in the evaluation
 #pragma unroll
-        for (int k1 = 0; k1 < LP; ++k1) ko[t_own + L2 * (k0 + k1)] = accI[k1];
+        for (int k1 = 0; k1 < LP; ++k1)
+          if (kok(k1)) ko[t_own + L2 * (k0 + k1)] = accI[k1];
       } else {
 #pragma unroll
-        for (int k1 = 0; k1 < LP; ++k1) ko[t_own + L2 * (k0 + k1)] += accI[k1];
+        for (int k1 = 0; k1 < LP; ++k1)
+          if (kok(k1)) ko[t_own + L2 * (k0 + k1)] += accI[k1];
       }
     }
   }
@@ -1783,9 +1814,10 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
       if (b >= tp.nJ) continue;
-      double* ko = kpsi + (size_t)(tp.J0 + b) * M3 + row;
+      double* ko = kpsi_s + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
-      for (int k1 = 0; k1 < LP; ++k1) ko[t_own + L2 * (k0 + k1)] += accJ[b][k1];
+      for (int k1 = 0; k1 < LP; ++k1)
+        if (kok(k1)) ko[t_own + L2 * (k0 + k1)] += accJ[b][k1];
     }
   }
   if (!want_e) return;
@@ -1810,7 +1842,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       double sum = 0.0;
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) sum += etot[w2];
-      e_part[(size_t)(t0 + blockIdx.y) * kparts + blockIdx.x] = sum;
+      e_part[(size_t)tp.eidx * kparts + blockIdx.x] = sum;
     }
   }
 }
@@ -1848,7 +1880,7 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
     const Slot* __restrict__ slots, const TilePair* __restrict__ tiles, int t0, int slot_base,
     cpx<double>* __restrict__ kpsi, double* __restrict__ e_part, int want_k, int want_e,
     int pair_out, const cpx<T>* __restrict__ twg, const cpx<T>* __restrict__ mdg, int kparts,
-    int swap_yz) {
+    int swap_yz, const SysTab systab) {
   using S = SplitAC<N>;
   constexpr int L1 = S::L1, L2 = S::L2;
   constexpr int P = N + 1;
@@ -1872,6 +1904,9 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
   const int y = blockIdx.x / (N / ZB);
   const int z0 = (blockIdx.x % (N / ZB)) * ZB;
   const TilePair tp = tiles[t0 + blockIdx.y];
+  // this tile pair's system (merged batch schedules) or the launch's own buffers
+  const double* __restrict__ occ_s = systab.n ? systab.occ[tp.sys] : occ;
+  cpx<double>* __restrict__ kpsi_s = systab.n ? reinterpret_cast<cpx<double>*>(systab.kpsi[tp.sys]) : kpsi;
   const size_t M3 = (size_t)N * N * N;
   const int t_own = tid % L2, zi_own = tid / L2;
   // offset of the owned row (swap_yz: spectrum (y, z) = grid (z, y))
@@ -1884,8 +1919,8 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
   }
   for (int k = tid; k < TM * TM; k += NT) smap[k / TM][k % TM] = -1;
   for (int k = tid; k < TM; k += NT) {
-    fI[k] = k < tp.nI ? occ[tp.I0 + k] : 0.0;
-    fJ[k] = k < tp.nJ ? occ[tp.J0 + k] : 0.0;
+    fI[k] = k < tp.nI ? occ_s[tp.I0 + k] : 0.0;
+    fJ[k] = k < tp.nJ ? occ_s[tp.J0 + k] : 0.0;
   }
   __syncthreads();
   for (int k = tid; k < ns; k += NT) {
@@ -2005,7 +2040,7 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
       ++k;
     }
     if (want_k) {
-      cpx<double>* ko = kpsi + (size_t)(tp.I0 + a) * M3 + row;
+      cpx<double>* ko = kpsi_s + (size_t)(tp.I0 + a) * M3 + row;
       if (tp.diag) {
         // on a diagonal tile orbital a's column sums (from rows a' < a) are
         // complete here: one write carries both
@@ -2033,7 +2068,7 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
       if (b >= tp.nJ) continue;
-      cpx<double>* ko = kpsi + (size_t)(tp.J0 + b) * M3 + row;
+      cpx<double>* ko = kpsi_s + (size_t)(tp.J0 + b) * M3 + row;
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
         cpx<double> v = ko[t_own + L2 * k1];
@@ -2065,7 +2100,7 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
       double sum = 0.0;
 #pragma unroll
       for (int w2 = 0; w2 < NW; ++w2) sum += etot[w2];
-      e_part[(size_t)(t0 + blockIdx.y) * kparts + blockIdx.x] = sum;
+      e_part[(size_t)tp.eidx * kparts + blockIdx.x] = sum;
     }
   }
 }
@@ -2145,6 +2180,32 @@ __global__ __launch_bounds__(1024) void k_finalize(const Slot* __restrict__ slot
     for (int w = 0; w < 16; ++w) s += red[w];
     *ex_out = -0.5 * s;
   }
+}
+
+// E_x of every member of a merged class (blockIdx.x = member): the sum of
+// k_finalize's mode 2 over the member's rows, in the same order
+__global__ __launch_bounds__(1024) void k_finalize_members(const MemberTab m,
+                                                           const double* __restrict__ e_slot, double h3) {
+  __shared__ double red[16];
+  const int tid = threadIdx.x, k = blockIdx.x;
+  const int r0 = m.row0[k], nvals = m.row0[k + 1] - r0;
+  double sum = 0.0;
+  for (int s = tid; s < nvals; s += 1024) sum += h3 * e_slot[r0 + s];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+  if ((tid & 63) == 0) red[tid >> 6] = sum;
+  __syncthreads();
+  if (tid == 0 && m.ex_out[k]) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += red[w];
+    *m.ex_out[k] = -0.5 * s;
+  }
+}
+
+hipError_t launch_finalize_members(const MemberTab& m, const double* e_slot, double h3, hipStream_t s) {
+  if (m.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize_members, dim3(m.n), dim3(1024), 0, s, m, e_slot, h3);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const Slot* slots, int nvals, const double* occ, const double* e_slot,
@@ -2471,8 +2532,9 @@ template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, int k_mode, bool want_e,
-                         bool pair_out, int tmax, const Tables& tb) {
+                         bool pair_out, int tmax, const Tables& tb, const SysTab* sys) {
   if (ntiles <= 0) return hipSuccess;
+  const SysTab systab = sys ? *sys : SysTab{};
   return dispatch_n(L.n, [&]<int N>() -> hipError_t {
     if constexpr (sizeof(T) == 8 && N > 96) {
       return hipErrorInvalidValue;
@@ -2490,11 +2552,13 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
         if (L.ncls == 2)
           hipLaunchKernelGGL((k_pass_c_cplx<T, N, 2, ZB, ZB * 16, TMC>), grid, dim3(ZB * 16), 0, L.stream, Xc,
                              pc, occ, slots, tiles, t0, slot_base, kc, e_slot, k_mode,
-                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz,
+                             systab);
         else
           hipLaunchKernelGGL((k_pass_c_cplx<T, N, 1, ZB, ZB * 16, TMC>), grid, dim3(ZB * 16), 0, L.stream, Xc,
                              pc, occ, slots, tiles, t0, slot_base, kc, e_slot, k_mode,
-                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz,
+                             systab);
         return hipGetLastError();
       }
       auto run = [&]<int HP>() -> hipError_t {
@@ -2504,11 +2568,13 @@ hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const dou
         if (L.ncls == 2)
           hipLaunchKernelGGL((k_pass_c<T, N, 2, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc,
                              psi, occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
-                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz,
+                             systab);
         else
           hipLaunchKernelGGL((k_pass_c<T, N, 1, ZB, NT, TM, HP>), grid, dim3(NT), 0, L.stream, Xc,
                              psi, occ, slots, tiles, t0, slot_base, kpsi, e_slot, k_mode,
-                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz);
+                             want_e ? 1 : 0, pair_out ? 1 : 0, tw, md, energy_parts(N), L.swap_yz,
+                             systab);
         return hipGetLastError();
       };
       if constexpr (pass_c_halves<T, N>() == 2) {
@@ -2531,10 +2597,11 @@ template hipError_t launch_pass_b_split<float>(const Launch&, void*, void*, int,
                                                const Tables&);
 template hipError_t launch_pass_c<float>(const Launch&, const void*, const float*, const double*,
                                          const Slot*, const TilePair*, int, int, int, double*,
-                                         double*, int, bool, bool, int, const Tables&);
+                                         double*, int, bool, bool, int, const Tables&,
+                                         const SysTab*);
 template hipError_t launch_pass_c<double>(const Launch&, const void*, const double*,
                                           const double*, const Slot*, const TilePair*, int, int,
                                           int, double*, double*, int, bool, bool, int,
-                                          const Tables&);
+                                          const Tables&, const SysTab*);
 
 }  // namespace exx

@@ -42,6 +42,33 @@ struct Launch {
   int swap_yz = 0; // spectrum (y, z) = grid (z, y): cy, cz above are then the grid's z and y classes
 };
 
+// Per-system outputs of a pass C launch over a merged batch schedule: K psi and
+// occupations of system k, each pointer offset back by the system's first
+// merged orbital so that merged orbital indices address it directly.  n = 0:
+// the launch's own kpsi and occ serve every tile pair.
+constexpr int kMaxMergedSystems = 32;
+struct SysTab {
+  int n = 0;
+  double* kpsi[kMaxMergedSystems] = {};
+  const double* occ[kMaxMergedSystems] = {};
+};
+
+// The members of a merged class for the launches that run once per class:
+// member k's FP64 orbitals psi[k] (count[k] values) go to the class's FP32 copy
+// at dst_off[k]; its energy rows are [row0[k], row0[k + 1]) and its E_x goes to
+// ex_out[k].
+struct MemberTab {
+  int n = 0;
+  const double* psi[kMaxMergedSystems] = {};
+  size_t count[kMaxMergedSystems] = {};
+  size_t dst_off[kMaxMergedSystems] = {};
+  int row0[kMaxMergedSystems + 1] = {};
+  double* ex_out[kMaxMergedSystems] = {};
+};
+hipError_t launch_convert_members(const MemberTab& m, float* psi32, size_t max_count, hipStream_t s);
+// E_x of every member from its rows of e_slot (as launch_finalize's sum mode 2)
+hipError_t launch_finalize_members(const MemberTab& m, const double* e_slot, double h3, hipStream_t s);
+
 }  // namespace exx
 
 struct exx_plan {
@@ -90,7 +117,8 @@ template <typename T>
 hipError_t launch_pass_c(const Launch& L, const void* X, const T* psi, const double* occ,
                          const Slot* slots, const TilePair* tiles, int t0, int ntiles,
                          int slot_base, double* kpsi, double* e_slot, int k_mode, bool want_e,
-                         bool pair_out, int tmax, const Tables& tb);  // k_mode: 0 none, 1 add, 2 diagonal tiles store
+                         bool pair_out, int tmax, const Tables& tb,
+                         const SysTab* sys = nullptr);  // k_mode: 0 none, 1 add, 2 diagonal tiles store
 // pass B in three launches through a scratch of ncls cy n^3 values per slot
 // (large slabs, FP32); used when pass_b_split() says so
 template <typename T>
@@ -118,6 +146,30 @@ hipError_t launch_gradient(double* grad_psi, size_t per_orb, int n_orb, const do
 int compute_impl(exx_plan* p, const double* psi, const double* occ, int n_orb, int mode,
                  unsigned flags, double* ex_out, double* kpsi, double* pair_e, void* ws,
                  size_t ws_bytes, void* stream, bool may_allocate);
+
+// Systems of one grid class of a batch evaluated with shared launches: one
+// merged schedule (merge_schedules) over the members' own schedules, so that
+// a pass A and a pass B launch cover a chunk of every member's slots and a
+// pass C launch a round of every member's tile pairs.  FP32 real or complex
+// plans of one grid; at most kMaxMergedSystems members.
+struct MergedClass {
+  std::vector<int> members;  // system indices of the batch
+  Schedule sched;            // merged; device copies in sched.d_slots / d_tiles
+  std::vector<int> orb_base, tile_base;
+  // workspace region of the class (offsets from the batch workspace) and its parts
+  size_t ws_off = 0, ws_bytes = 0;
+  size_t psi32 = 0, e_part = 0, e_slot = 0, X = 0, Y = 0;
+  int split_slots = 0;
+};
+// Builds the merged schedule of `members` (their plans prepared for their
+// orbital counts), uploads it and sizes the class workspace.
+int build_merged_class(const std::vector<exx_plan*>& plans, const std::vector<int>& n_orb,
+                       MergedClass& mc);
+void free_merged_class(MergedClass& mc);
+// One evaluation of the class in KPSI or ENERGY_KPSI mode without pair
+// energies (sys: the batch's systems; ws: the batch workspace).
+int run_merged_class(const std::vector<exx_plan*>& plans, const MergedClass& mc,
+                     const exx_system* sys, int mode, unsigned flags, char* ws, hipStream_t st);
 
 // Record msg (or the HIP error) as this thread's exx_last_error() and return
 // the code (EXX_ERR_HIP for the second).

@@ -33,6 +33,28 @@ std::vector<std::vector<std::pair<int, int>>> tile_rounds(int nt) {
   return rounds;
 }
 
+// Chunks of whole tile pairs whose slots fit `cap`, each split into segments
+// (runs of one round) for the pass C launches.
+static void chunk_tiles(Schedule& s, int cap) {
+  int t0 = 0;
+  while (t0 < (int)s.tiles.size()) {
+    int t1 = t0;
+    while (t1 < (int)s.tiles.size() && s.tiles[t1].s1 - s.tiles[t0].s0 <= cap) ++t1;
+    if (t1 == t0) t1 = t0 + 1;
+    Schedule::Chunk c{t0, t1, s.tiles[t0].s0, s.tiles[t1 - 1].s1, (int)s.segments.size(), 0};
+    int a = t0;
+    while (a < t1) {
+      int b = a;
+      while (b < t1 && s.tile_round[b] == s.tile_round[a]) ++b;
+      s.segments.push_back({a, b});
+      a = b;
+    }
+    c.seg1 = (int)s.segments.size();
+    s.chunks.push_back(c);
+    t0 = t1;
+  }
+}
+
 void build_schedule_host(int N, int T, int batch_slots, int packing, Schedule& s) {
   s = Schedule();
   s.n_orb = N;
@@ -83,29 +105,62 @@ void build_schedule_host(int N, int T, int batch_slots, int packing, Schedule& s
           if (sl.ia >= 0 || sl.ib >= 0) s.slots.push_back(sl);
         }
       tp.s1 = (int)s.slots.size();
+      tp.sys = 0;
+      tp.eidx = (int)s.tiles.size();
       s.tiles.push_back(tp);
       round_of.push_back((int)r);
     }
+  s.tile_round = round_of;
   // chunks of whole tile pairs whose slots fit the launch capacity; pass C
   // segments split chunks at round boundaries
   const int cap = std::max(batch_slots, packing == kTiled ? T * T : T * ((T + 1) / 2));
-  int t0 = 0;
-  while (t0 < (int)s.tiles.size()) {
-    int t1 = t0;
-    while (t1 < (int)s.tiles.size() && s.tiles[t1].s1 - s.tiles[t0].s0 <= cap) ++t1;
-    if (t1 == t0) t1 = t0 + 1;
-    Schedule::Chunk c{t0, t1, s.tiles[t0].s0, s.tiles[t1 - 1].s1, (int)s.segments.size(), 0};
-    int a = t0;
-    while (a < t1) {
-      int b = a;
-      while (b < t1 && round_of[b] == round_of[a]) ++b;
-      s.segments.push_back({a, b});
-      a = b;
-    }
-    c.seg1 = (int)s.segments.size();
-    s.chunks.push_back(c);
-    t0 = t1;
+  chunk_tiles(s, cap);
+}
+
+void merge_schedules(const std::vector<const Schedule*>& parts, int cap, Schedule& out,
+                     std::vector<int>& orb_base, std::vector<int>& tile_base) {
+  out = Schedule();
+  orb_base.assign(parts.size(), 0);
+  tile_base.assign(parts.size(), 0);
+  int rounds = 0, orbs = 0, tiles = 0;
+  for (size_t k = 0; k < parts.size(); ++k) {
+    orb_base[k] = orbs;
+    tile_base[k] = tiles;
+    orbs += parts[k]->n_orb;
+    tiles += (int)parts[k]->tiles.size();
+    rounds = std::max(rounds, parts[k]->n_rounds);
+    out.n_pairs += parts[k]->n_pairs;
   }
+  out.n_orb = orbs;
+  out.n_rounds = rounds;
+  out.tile = parts.empty() ? 0 : parts[0]->tile;
+  out.batch_slots = cap;
+  auto shift = [](int i, int b) { return i < 0 ? i : i + b; };
+  int max_tile_slots = 1;
+  for (int r = 0; r < rounds; ++r)
+    for (size_t k = 0; k < parts.size(); ++k) {
+      const Schedule& p = *parts[k];
+      const int b = orb_base[k];
+      for (size_t t = 0; t < p.tiles.size(); ++t) {
+        if (p.tile_round[t] != r) continue;
+        TilePair tp = p.tiles[t];
+        const int s0 = (int)out.slots.size();
+        for (int s = tp.s0; s < tp.s1; ++s) {
+          const Slot& sl = p.slots[s];
+          out.slots.push_back({shift(sl.ia, b), shift(sl.ja, b), shift(sl.ib, b), shift(sl.jb, b)});
+        }
+        tp.s0 = s0;
+        tp.s1 = (int)out.slots.size();
+        tp.I0 += b;
+        tp.J0 += b;
+        tp.sys = (int)k;
+        tp.eidx = tile_base[k] + (int)t;
+        max_tile_slots = std::max(max_tile_slots, tp.s1 - tp.s0);
+        out.tiles.push_back(tp);
+        out.tile_round.push_back(r);
+      }
+    }
+  chunk_tiles(out, std::max(cap, max_tile_slots));
 }
 
 }  // namespace exx

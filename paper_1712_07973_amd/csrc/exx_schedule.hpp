@@ -17,9 +17,11 @@ struct Slot {
 };
 
 // One pair tile: orbitals [I0, I0+nI) x [J0, J0+nJ) (upper triangle when
-// diag), its slots [s0, s1).
+// diag), its slots [s0, s1).  sys: the system of a merged batch schedule (0
+// otherwise); eidx: the row of its energy partials (the tile index within its
+// system plus the system's first row).
 struct TilePair {
-  int s0, s1, I0, nI, J0, nJ, diag, pad;
+  int s0, s1, I0, nI, J0, nJ, diag, sys, eidx, pad;
 };
 
 struct Schedule {
@@ -39,6 +41,7 @@ struct Schedule {
   };
   std::vector<Chunk> chunks;
   std::vector<Segment> segments;
+  std::vector<int> tile_round;  // round of each tile pair
   int n_rounds = 0;
   Slot* d_slots = nullptr;
   TilePair* d_tiles = nullptr;
@@ -54,6 +57,18 @@ enum Packing {
 
 // Builds the schedule for n_orb orbitals.
 void build_schedule_host(int n_orb, int tile, int batch_slots, int packing, Schedule& s);
+
+// One schedule over several systems of one grid (a batch's grid class): the
+// tile pairs of round r of every system, system by system, then round r + 1,
+// so that one pass C launch covers a round of every system.  Orbital indices
+// become indices into the systems' orbitals laid end to end (system k's
+// orbital i is orb_base[k] + i); each tile pair keeps its system in `sys` and
+// its energy row tile_base[sys] + (its index in that system's schedule) in
+// `eidx`.  Chunks hold whole tile pairs within `cap` slots (at least one tile
+// pair), split into segments at round boundaries as in build_schedule_host.
+// The per-system schedules must share one packing.
+void merge_schedules(const std::vector<const Schedule*>& parts, int cap, Schedule& out,
+                     std::vector<int>& orb_base, std::vector<int>& tile_base);
 
 // Rounds of a round-robin tournament over nt tiles; the first round holds the
 // diagonal pairs (I, I).  No two pairs of one round share a tile.

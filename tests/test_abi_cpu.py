@@ -81,14 +81,18 @@ def test_plan_validation_precision_and_counts(lib):
     gp.kernel = 2
     assert lib.exx_plan_create(C.byref(h), C.byref(gp), 0, 16, 0) == -1
     assert b"ISF" in lib.exx_last_error()
-    # plan flags: only EXX_PLAN_COMPLEX (1) is defined; batch flags: GRAPH (1), COMPLEX (2)
+    # plan flags: only EXX_PLAN_COMPLEX (1) is defined; batch flags: GRAPH (1),
+    # COMPLEX (2), MERGE (4, FP32 only)
     assert lib.exx_plan_create(C.byref(h), C.byref(g), 0, 16, 2) == -1
     assert b"flags" in lib.exx_last_error()
     grids = (type(g) * 1)(g)
     counts = (C.c_int * 1)(4)
-    assert lib.exx_batch_create(C.byref(h), grids, counts, 1, 0, 4) == -1
+    assert lib.exx_batch_create(C.byref(h), grids, counts, 1, 0, 8) == -1
     assert not h.value
     assert b"batch flags" in lib.exx_last_error()
+    assert lib.exx_batch_create(C.byref(h), grids, counts, 1, 2, 4) == -1
+    assert not h.value
+    assert b"FP32" in lib.exx_last_error()
 
 
 def test_null_plan_calls(lib):

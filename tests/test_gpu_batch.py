@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from gpu_common import grid_of, say, small_system
 
 pytestmark = pytest.mark.gpu
@@ -133,3 +134,70 @@ def test_batch_autotune_per_grid_class(use_graph):
             torch.cuda.synchronize()
             assert ex.item() == e1.item()
             assert torch.equal(kp, k1)
+
+
+MERGE_CASES = [("free", 32, 5, 91), ("free", 32, 9, 92), ("free", 48, 4, 93), ("free", 32, 2, 94),
+               ("periodic", 32, 3, 95), ("free", 48, 7, 96), ("free", 32, 1, 97)]
+
+
+def _merge_inputs(cases, complex_orbitals=False):
+    dev = torch.device("cuda", 0)
+    kmax = 0.4 if complex_orbitals else 0.0
+    systems = [small_system(bc, n, N, seed, kmax=kmax) for bc, n, N, seed in cases]
+    psis = [torch.from_numpy(s.psi).to(dev) for s in systems]
+    occs = [torch.from_numpy(s.occ).to(dev) for s in systems]
+    return systems, psis, occs
+
+
+@pytest.mark.parametrize("complex_orbitals", [False, True])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_merged_batch_equals_unmerged(use_graph, complex_orbitals):
+    # systems on one grid share their pass launches (merged round-robin rounds);
+    # every system's E_x and K psi equal the unmerged batch's bit for bit, on
+    # every replay, with other eager work between the calls
+    say(f"[merged batch] graph={use_graph} complex={complex_orbitals}")
+    systems, psis, occs = _merge_inputs(MERGE_CASES, complex_orbitals)
+    grids = [grid_of(s) for s in systems]
+    ns = [s.n_orb for s in systems]
+    ref = exx.Batch(grids, ns, "fp32", use_graph=False, complex_orbitals=complex_orbitals)
+    want = [(e.item(), k.clone()) for e, k in ref.compute(psis, occs, "energy_kpsi")]
+    del ref
+    b = exx.Batch(grids, ns, "fp32", use_graph=use_graph, complex_orbitals=complex_orbitals,
+                  merge=True)
+    outs = None
+    for rep in range(3):
+        outs = b.compute(psis, occs, "energy_kpsi", outputs=outs)
+        torch.cuda.synchronize()
+        for (ex, kp), (E1, K1) in zip(outs, want):
+            assert ex.item() == E1
+            assert torch.equal(kp, K1)
+        x = torch.randn(1 << 20, device=psis[0].device)
+        (x * 2).sum().item()
+        for ex, kp in outs:
+            kp.fill_(123.0)
+            ex.fill_(7.0)
+    # K psi only, and accumulation into K psi
+    outs = b.compute(psis, occs, "kpsi", outputs=outs)
+    torch.cuda.synchronize()
+    for (_, kp), (_, K1) in zip(outs, want):
+        assert torch.equal(kp, K1)
+
+
+def test_merged_batch_matches_oracle_and_limits():
+    say("[merged batch] oracle, 34 systems on one grid, refusals")
+    cases = [("free", 16, 1 + k % 3, 200 + k) for k in range(34)] + [("free", 32, 5, 91)]
+    systems, psis, occs = _merge_inputs(cases)
+    b = exx.Batch([grid_of(s) for s in systems], [s.n_orb for s in systems], "fp32",
+                  use_graph=True, merge=True)
+    outs = b.compute(psis, occs, "energy_kpsi")
+    torch.cuda.synchronize()
+    for k in (0, 17, 33, 34):  # both 16^3 classes (32 + 2 systems) and the 32^3 one
+        s = systems[k]
+        ref = oracle.exx(s.psi, s.occ, s.h, s.bc, symmetric=True)
+        E, K = outs[k][0].item(), outs[k][1].cpu().numpy()
+        assert abs(E - ref["E"]) / s.n_orb < 1e-6
+        assert np.max(np.abs(K - ref["kpsi"])) <= 1e-5 * np.max(np.abs(ref["kpsi"]))
+    with pytest.raises(exx.ExxError):
+        b.compute(psis, occs, "energy")
+    with pytest.raises(exx.ExxError):
+        exx.Batch([grid_of(s) for s in systems[:2]], [1, 1], "fp64_fused", merge=True)

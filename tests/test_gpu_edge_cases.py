@@ -12,8 +12,8 @@
 * batches of real-orbital systems against the oracle, not only against
   single-system calls;
 * a negative occupation in the energy-only mode (signed weights kept);
-* both thread splits of pass C at n = 96 and 128 (tile 4: one thread per row
-  segment; tile 8: two).
+* both thread splits of pass C from n = 96 on (tile 4: one thread per row
+  segment; tile 8: two, unevenly at n = 112).
 """
 import numpy as np
 import pytest
@@ -77,11 +77,14 @@ def test_slab_forms_match_oracle(case, form):
 
 
 @pytest.mark.parametrize("tile", [4, 8])
-@pytest.mark.parametrize("bc,n,N,seed", [("free", 96, 6, 81), ("free", 128, 5, 82),
-                                         ("periodic", 128, 5, 83)])
+@pytest.mark.parametrize("bc,n,N,seed", [("free", 80, 6, 84), ("free", 96, 6, 81),
+                                         ("free", 112, 5, 85), ("free", 128, 5, 82),
+                                         ("periodic", 112, 5, 86), ("periodic", 128, 5, 83)])
 def test_pass_c_thread_split_matches_oracle(bc, n, N, seed, tile):
-    # at n = 96, 128 a tile of 4 runs pass C with one thread per row segment
-    # (256 threads), a tile of 8 with two threads per segment (512 threads)
+    # from n = 96 on a tile of 4 runs pass C with one thread per row segment
+    # (256 threads), a tile of 8 with two threads per segment (512 threads); at
+    # n = 112 the segment's n / 16 points split unevenly between the two (n = 80
+    # has the one-thread form only, at both tiles)
     say(f"[pass C split] fp32 tile={tile} {bc} n={n} N={N} seed={seed}")
     s, ref = oracle_result(bc, n, N, seed, 1)
     psi, occ = _tensors(s)

@@ -153,3 +153,67 @@ def test_odd_chunks_with_an_off_diagonal_tile_pair(probe):
     assert any(r["T"][t][6] == 0 for t in range(t0, t1))  # an off-diagonal tile pair
     off = [t for t in range(t0, t1) if r["T"][t][6] == 0][0]
     assert r["T"][off][1] - r["T"][off][0] == 3  # three rows of one column pair
+
+
+def run_merged(probe, cap, packing, T, sizes):
+    out = subprocess.run([probe, "merge", str(cap), str(packing), str(T), *map(str, sizes)],
+                         capture_output=True, text=True, check=True).stdout.split("\n")
+    rec = {"B": [], "S": [], "T": [], "C": [], "G": []}
+    for line in out:
+        if not line:
+            continue
+        k, *v = line.split()
+        if k != "P":
+            rec[k].append(tuple(int(x) for x in v))
+    return rec
+
+
+@pytest.mark.parametrize("packing", [PACKED, TILED])
+@pytest.mark.parametrize("cap,T,sizes", [(40, 4, [5, 9, 3]), (1 << 20, 8, [22, 39, 67, 70]),
+                                         (64, 8, [1, 2, 17, 8]), (3, 4, [7, 7])])
+def test_merged_schedule_of_several_systems(probe, cap, T, sizes, packing):
+    r = run_merged(probe, cap, packing, T, sizes)
+    base = [b[0] for b in r["B"]]
+    tbase = [b[1] for b in r["B"]]
+    ntiles = [b[2] for b in r["B"]]
+    assert base == [sum(sizes[:k]) for k in range(len(sizes))]
+    # every pair of every system exactly once, in global indices of its own system
+    seen = []
+    for t in r["T"]:
+        s0, s1, I0, nI, J0, nJ, diag, sys, eidx, rnd = t
+        lo, hi = base[sys], base[sys] + sizes[sys]
+        assert lo <= I0 < hi and lo <= J0 < hi and I0 + nI <= hi and J0 + nJ <= hi
+        for sl in r["S"][s0:s1]:
+            for i, j in (sl[:2], sl[2:]):
+                if i < 0:
+                    continue
+                assert I0 <= i < I0 + nI and J0 <= j < J0 + nJ
+                seen.append((sys, i - lo, j - lo))
+    want = [(k, i, j) for k, N in enumerate(sizes) for i in range(N) for j in range(i, N)]
+    assert sorted(seen) == sorted(want)
+    # energy rows: system k owns tbase[k] .. tbase[k] + ntiles[k] - 1, one per tile pair
+    for k in range(len(sizes)):
+        rows = sorted(t[8] for t in r["T"] if t[7] == k)
+        assert rows == list(range(tbase[k], tbase[k] + ntiles[k]))
+    # rounds are in order, so every system's diagonal tile pairs (round 0) come
+    # before its other tile pairs; a segment is one round and orbital-disjoint
+    rounds = [t[9] for t in r["T"]]
+    assert rounds == sorted(rounds)
+    assert all(t[6] == (t[9] == 0) for t in r["T"])
+    for g0, g1 in r["G"]:
+        tiles = r["T"][g0:g1]
+        assert len({t[9] for t in tiles}) == 1
+        used = set()
+        for t in tiles:
+            orbs = set(range(t[2], t[2] + t[3])) | set(range(t[4], t[4] + t[5]))
+            assert not (orbs & used)
+            used |= orbs
+    # chunks cover the tile pairs and slots contiguously within the capacity
+    # (or one tile pair larger than it)
+    t_next, s_next = 0, 0
+    for t0, t1, s0, s1, g0, g1 in r["C"]:
+        assert t0 == t_next and s0 == s_next and t1 > t0
+        assert s1 - s0 <= cap or t1 == t0 + 1
+        assert r["G"][g0][0] == t0 and r["G"][g1 - 1][1] == t1
+        t_next, s_next = t1, s1
+    assert t_next == len(r["T"]) and s_next == len(r["S"])
