@@ -41,6 +41,32 @@ __device__ __forceinline__ int fold(int k, int M) { return k <= M - k ? k : M - 
 // z-block of the spectrum layout; passes A and C move one z-block of rows
 constexpr int XZ = 16;
 
+// Block b of a one-dimensional grid over R items (row blocks or slabs) times G
+// slot groups.  Workgroups are dealt to the eight XCDs in turn (b mod 8); each
+// XCD takes a contiguous eighth of the items and walks the slot groups of one
+// item before the next, so the blocks resident on one XCD at a time share what
+// depends on the item only (orbital rows in pass A, the kernel plane in pass B)
+// in that XCD's L2.  The blocks in flight then also spread over every slot of
+// the launch instead of a few, which costs where a slot is large: measured
+// same-box, 32 and 64 orbitals, ms per evaluation (row-major -> XCD order):
+//   pass A  free 64^3: 0.224 -> 0.209    free 128^3: 8.82 -> 9.60 (64 orbitals)
+//   pass B  free 64^3: 1.284 -> 1.310    free 128^3: 48.7 -> 48.2, and pass C
+//           after it 14.2 -> 13.8 (its spectrum reads follow pass B's writes)
+// so pass A takes it up to n = 64 and the wave-local pass B from n = 96 on.
+constexpr int NXCD = 8;
+constexpr bool pass_a_xcd_order(int n) { return n <= 64; }
+constexpr bool pass_b_xcd_order(int n) { return n >= 96; }
+__device__ __forceinline__ void xcd_split(int b, int R, int G, int& r, int& g) {
+  if (R % NXCD == 0) {
+    const int x = b % NXCD, i = b / NXCD;
+    g = i % G;
+    r = x * (R / NXCD) + i / G;
+  } else {
+    g = b % G;
+    r = b / G;
+  }
+}
+
 // slots per pass A block.  With the non-temporal spectrum stores, up to n = 64 more
 // blocks beat reusing a block's set-up (64^3, 32 orbitals: pass A 0.178 ms with one
 // slot, 0.212 with 2, 0.219 with 4); larger grids already launch enough blocks per
@@ -155,9 +181,16 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
   __shared__ cpx<T> md[N];
 
   const int tid = threadIdx.x;
-  const int y = blockIdx.x / (N / ZB);
-  const int z0 = (blockIdx.x % (N / ZB)) * ZB;
-  const int ls0 = blockIdx.y * SPB;
+  int rb, sg;  // row block (y, z-block) and slot group
+  if constexpr (pass_a_xcd_order(N)) {
+    xcd_split(blockIdx.x, N * (N / ZB), (nslots + SPB - 1) / SPB, rb, sg);
+  } else {
+    rb = blockIdx.x;
+    sg = blockIdx.y;
+  }
+  const int y = rb / (N / ZB);
+  const int z0 = (rb % (N / ZB)) * ZB;
+  const int ls0 = sg * SPB;
   const int ls1 = ls0 + SPB < nslots ? ls0 + SPB : nslots;
   const size_t M3 = (size_t)N * N * N;
 
@@ -1166,7 +1199,7 @@ __global__ __launch_bounds__(8 * N) void k_pass_b_wave(cpx<T>* __restrict__ X,
                                                        const cpx<T>* __restrict__ twg,
                                                        const cpx<T>* __restrict__ mdg,
                                                        double* __restrict__ e_slot, int slot0,
-                                                       int kparts) {
+                                                       int kparts, int nslots) {
   constexpr int NT = 8 * N, L1 = N / 8, PB = wave_pitch<N>();
   constexpr int MX = CX * N, MY = CY * N, MZ = CZ * N;
   constexpr int HY = MY / 2 + 1, HZ = MZ / 2 + 1;
@@ -1178,8 +1211,13 @@ __global__ __launch_bounds__(8 * N) void k_pass_b_wave(cpx<T>* __restrict__ X,
   __shared__ __align__(16) cpx<T> colA[L1 * WAVE_TA];
 
   const int tid = threadIdx.x;
-  const int slab = blockIdx.x;  // cx * N + kx
-  const int ls = blockIdx.y;
+  int slab, ls;  // slab = cx * N + kx, slot of the launch
+  if constexpr (pass_b_xcd_order(N)) {
+    xcd_split(blockIdx.x, CX * N, nslots, slab, ls);
+  } else {
+    slab = blockIdx.x;
+    ls = blockIdx.y;
+  }
   const int cx = slab / N, kxp = slab % N;
   const int kxf = CX == 2 ? 2 * kxp + cx : kxp;
   const T* kt = ktab + (size_t)fold(kxf, MX) * HY * HZ;
@@ -2312,7 +2350,8 @@ hipError_t launch_pass_a(const Launch& L, const T* psi, void* X, const Slot* slo
     constexpr int ZB = XZ;
     constexpr int NT = 256;
     constexpr int SPB = pass_a_slots(N);
-    dim3 grid(N * (N / ZB), (nslots + SPB - 1) / SPB);
+    dim3 grid = pass_a_xcd_order(N) ? dim3(N * (N / ZB) * ((nslots + SPB - 1) / SPB))
+                            : dim3(N * (N / ZB), (nslots + SPB - 1) / SPB);
     auto* Xc = static_cast<cpx<T>*>(X);
     auto* tw = static_cast<const cpx<T>*>(tb.tw);
     auto* md = static_cast<const cpx<T>*>(tb.md);
@@ -2387,13 +2426,13 @@ hipError_t launch_pass_b_wave(const Launch& L, cpx<T>* Xc, int nslots, bool ener
     auto* kt = static_cast<const T*>(tb.ktab);
     auto* tw = static_cast<const cpx<T>*>(tb.tw);
     auto* md = static_cast<const cpx<T>*>(tb.md);
-    dim3 grid(CX * N, nslots);
+    dim3 grid = pass_b_xcd_order(N) ? dim3(CX * N * nslots) : dim3(CX * N, nslots);
     if (energy_only)
       hipLaunchKernelGGL((k_pass_b_wave<T, N, CX, CY, CZ, true>), grid, dim3(8 * N), 0, L.stream,
-                         Xc, kt, tw, md, e_slot, slot0, energy_parts(N));
+                         Xc, kt, tw, md, e_slot, slot0, energy_parts(N), nslots);
     else
       hipLaunchKernelGGL((k_pass_b_wave<T, N, CX, CY, CZ, false>), grid, dim3(8 * N), 0, L.stream,
-                         Xc, kt, tw, md, e_slot, slot0, energy_parts(N));
+                         Xc, kt, tw, md, e_slot, slot0, energy_parts(N), nslots);
     return hipGetLastError();
   }
 }
