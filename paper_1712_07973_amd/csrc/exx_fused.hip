@@ -1185,7 +1185,14 @@ __device__ __forceinline__ void wave_y_class(cpx<T>* __restrict__ S, const WaveT
       for (int k1 = 0; k1 < L1; ++k1) {
         cpx<T>* dst = reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(g) + off2 + (size_t)k1 * KSTRIDE);
         if (CY == 2) o[k1] = cadd(o[k1], HOLD ? P[k1] : pk[(EARLY && !HOLD) ? k1 : 0]);
-        *dst = o[k1];
+        // pass C reads the result only after the launch: at n = 128 a
+        // non-temporal store keeps it from evicting what the blocks in flight
+        // re-read (kernel planes, parked and class-1 slab data; pass B -1 %,
+        // no gain at n <= 96)
+        if constexpr (N >= 128)
+          store_stream(dst, o[k1]);
+        else
+          *dst = o[k1];
       }
     }
   }
