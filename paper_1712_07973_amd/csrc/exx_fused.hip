@@ -890,11 +890,14 @@ constexpr int wave_pitch() {
   return p;
 }
 
-// The two-class output of the y classes is held in registers (instead of being
-// parked in the slab) while a thread's value count stays small.
+// The class-0 output of the y classes is held in registers (instead of being
+// parked in the slab and read back) where the registers allow it: up to n = 64,
+// and at n = 96, whose 768-thread block (3 waves per SIMD) may use 168 registers
+// a lane (143 with the held values; pass B -5 % at free 96^3).  The 896- and
+// 1024-thread blocks of n = 112, 128 have 128, all in use.
 template <typename T, int N>
 constexpr bool wave_hold_p0() {
-  return sizeof(T) == 4 && N <= 64;
+  return sizeof(T) == 4 && (N <= 64 || N == 96);
 }
 
 // A value the compiler must treat as unknown from here on: keeps it from
