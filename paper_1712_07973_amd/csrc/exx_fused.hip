@@ -41,31 +41,18 @@ __device__ __forceinline__ int fold(int k, int M) { return k <= M - k ? k : M - 
 // z-block of the spectrum layout; passes A and C move one z-block of rows
 constexpr int XZ = 16;
 
-// Block b of a one-dimensional grid over R items (row blocks or slabs) times G
-// slot groups.  Workgroups are dealt to the eight XCDs in turn (b mod 8); each
-// XCD takes a contiguous eighth of the items and walks the slot groups of one
-// item before the next, so the blocks resident on one XCD at a time share what
-// depends on the item only (orbital rows in pass A, the kernel plane in pass B)
-// in that XCD's L2.  The blocks in flight then also spread over every slot of
-// the launch instead of a few, which costs where a slot is large: measured
-// same-box, 32 and 64 orbitals, ms per evaluation (row-major -> XCD order):
+// XCD-ordered grids (xcd_split, exx_schedule.hpp): the blocks resident on one
+// XCD at a time share what depends on the item only (orbital rows in pass A,
+// the kernel plane in pass B) in that XCD's L2.  The blocks in flight then also
+// spread over every slot of the launch instead of a few, which costs where a
+// slot is large: measured same-box, 32 and 64 orbitals, ms per evaluation
+// (row-major -> XCD order):
 //   pass A  free 64^3: 0.224 -> 0.209    free 128^3: 8.82 -> 9.60 (64 orbitals)
 //   pass B  free 64^3: 1.284 -> 1.310    free 128^3: 48.7 -> 48.2, and pass C
 //           after it 14.2 -> 13.8 (its spectrum reads follow pass B's writes)
 // so pass A takes it up to n = 64 and the wave-local pass B from n = 96 on.
-constexpr int NXCD = 8;
 constexpr bool pass_a_xcd_order(int n) { return n <= 64; }
 constexpr bool pass_b_xcd_order(int n) { return n >= 96; }
-__device__ __forceinline__ void xcd_split(int b, int R, int G, int& r, int& g) {
-  if (R % NXCD == 0) {
-    const int x = b % NXCD, i = b / NXCD;
-    g = i % G;
-    r = x * (R / NXCD) + i / G;
-  } else {
-    g = b % G;
-    r = b / G;
-  }
-}
 
 // slots per pass A block.  With the non-temporal spectrum stores, up to n = 64 more
 // blocks beat reusing a block's set-up (64^3, 32 orbitals: pass A 0.178 ms with one

@@ -74,4 +74,23 @@ void merge_schedules(const std::vector<const Schedule*>& parts, int cap, Schedul
 // diagonal pairs (I, I).  No two pairs of one round share a tile.
 std::vector<std::vector<std::pair<int, int>>> tile_rounds(int nt);
 
+// Launch order of a one-dimensional grid over R items (row blocks or slabs)
+// times G slot groups: block b -> (item r, slot group g).  Workgroups are dealt
+// to the device's XCDs in turn (b mod kXcds); each XCD takes a contiguous share
+// of R / kXcds items and walks the slot groups of one item before the next.  A
+// bijection of [0, R G) onto the pairs; for R not a multiple of kXcds, slot
+// groups fastest over the whole grid.  (Used by the kernels; constexpr so that
+// host code can check it.)
+constexpr int kXcds = 8;
+constexpr void xcd_split(int b, int R, int G, int& r, int& g) {
+  if (R % kXcds == 0) {
+    const int x = b % kXcds, i = b / kXcds;
+    g = i % G;
+    r = x * (R / kXcds) + i / G;
+  } else {
+    g = b % G;
+    r = b / G;
+  }
+}
+
 }  // namespace exx

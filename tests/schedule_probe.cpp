@@ -2,7 +2,7 @@
 // the host-side schedule tests:  S ia ja ib jb / T s0 s1 I0 nI J0 nJ diag /
 // C t0 t1 s0 s1 seg0 seg1 / G t0 t1.  With "merge" first, the merged schedule
 // of several systems (B orb_base tile_base n_tiles per system; T lines add sys,
-// eidx and the round).
+// eidx and the round); with "xcd R G", the XCD-ordered launch map.
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -37,6 +37,16 @@ static int merged(int argc, char** argv) {
 
 int main(int argc, char** argv) {
   if (argc >= 6 && std::string(argv[1]) == "merge") return merged(argc, argv);
+  if (argc == 4 && std::string(argv[1]) == "xcd") {
+    // xcd <R> <G>: the launch order, one line X b r g per block
+    const int R = std::atoi(argv[2]), G = std::atoi(argv[3]);
+    for (int b = 0; b < R * G; ++b) {
+      int r = -1, g = -1;
+      exx::xcd_split(b, R, G, r, g);
+      std::printf("X %d %d %d\n", b, r, g);
+    }
+    return 0;
+  }
   if (argc < 5) return 2;
   int N = std::atoi(argv[1]), T = std::atoi(argv[2]), cap = std::atoi(argv[3]);
   int packing = std::atoi(argv[4]);  // exx::Packing

@@ -217,3 +217,22 @@ def test_merged_schedule_of_several_systems(probe, cap, T, sizes, packing):
         assert r["G"][g0][0] == t0 and r["G"][g1 - 1][1] == t1
         t_next, s_next = t1, s1
     assert t_next == len(r["T"]) and s_next == len(r["S"])
+
+
+@pytest.mark.parametrize("R,G", [(1024, 64), (256, 128), (144, 5), (64, 1), (784, 3), (36, 7)])
+def test_xcd_ordered_launch_map(probe, R, G):
+    """The XCD-ordered grid of passes A and B covers every (item, slot group)
+    once; for R a multiple of 8, the blocks one XCD receives (b = x mod 8) stay
+    within its contiguous eighth of the items and take an item's slot groups in
+    turn before the next item."""
+    out = subprocess.run([probe, "xcd", str(R), str(G)], capture_output=True, text=True,
+                         check=True).stdout.split()
+    rows = [tuple(int(v) for v in out[k + 1:k + 4]) for k in range(0, len(out), 4)]
+    assert len(rows) == R * G
+    assert sorted((r, g) for _, r, g in rows) == [(r, g) for r in range(R) for g in range(G)]
+    if R % 8:
+        return
+    for x in range(8):
+        seq = [(r, g) for b, r, g in rows if b % 8 == x]
+        assert all(x * (R // 8) <= r < (x + 1) * (R // 8) for r, _ in seq)
+        assert seq == sorted(seq)  # item-major, slot groups fastest
