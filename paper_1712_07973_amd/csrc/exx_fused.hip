@@ -1624,15 +1624,16 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   constexpr int HB = (TM + 1) / 2;            // column pairs per tile row
   constexpr int MAXS = TM * HB;               // slots per tile pair
   constexpr int NW = NT / 64;
-  constexpr int PF = (NL * N + NT - 1) / NT;  // prefetched spectrum values per thread
+  constexpr int C2 = NL * L1;                 // step-2 items (line, q1), one per thread
   constexpr int LP = (L1 + HP - 1) / HP;      // points per thread (the last half may own one less)
   constexpr bool EVEN = L1 % HP == 0;
   static_assert(ZB * L2 * HP == NT, "HP point-owner threads per (row, t)");
   static_assert(ZB == XZ, "a block's rows are one z-block of the spectrum layout");
-  // Spectrum rows of the current slot.  One buffer suffices: the store of
-  // slot k+1 follows the second barrier of slot k, after every read of xs.
-  __shared__ cpx<T> xs[NL * P];
-  __shared__ cpx<T> xo[NL * P];     // after the inverse step 2
+  static_assert(C2 <= NT, "one step-2 item per thread");
+  // Rows after the inverse step 2, two buffers: slot k's step 1 reads buffer
+  // k & 1 while the step-2 threads fill the other one for slot k + 1, and the
+  // one barrier per slot orders the step 1 of slot k - 1 before that fill.
+  __shared__ cpx<T> xo[2][NL * P];
   __shared__ cpx<T> tw[N];
   __shared__ cpx<T> md[N];
   __shared__ Slot st[MAXS];
@@ -1692,14 +1693,19 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   double ew = 0.0;
 
   // spectrum rows of a slot: the block's rows are one contiguous z-block chunk
-  // of the slot, values p = tid + q NT -> (cx, kx, zi), zi fastest
-  cpx<T> pf[PF];
+  // of the slot, value (cx, kx, zi) at (cx N + kx) ZB + zi.  Step-2 item (line,
+  // q1) = (tid mod NL, tid / NL), line = cx ZB + zi, takes kx = q1 + L1 q2: its
+  // thread loads them straight into registers, one slot ahead (a wavefront's
+  // loads are 256-byte runs of two kx at 16 zi)
+  const bool s2 = tid < C2;
+  const int line2 = tid % NL, q12 = tid / NL;
+  cpx<T> nw[L2];
   auto fetch = [&](int k) {
-    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N;
+    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N +
+                       (size_t)((line2 / ZB) * N + q12) * ZB + line2 % ZB;
+    if (s2) {
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      int p = tid + q * NT;
-      if ((NL * N) % NT == 0 || p < NL * N) pf[q] = load_stream(Xs + p);
+      for (int q2 = 0; q2 < L2; ++q2) nw[q2] = load_stream(Xs + (size_t)L1 * q2 * ZB);
     }
   };
   // orbital values at the owned points: every J-side orbital of the tile once
@@ -1732,31 +1738,19 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 #pragma unroll
     for (int bb = 0; bb < HB; ++bb) {
       if (smap[a][bb] < 0) continue;
-      cpx<T>* xb = xs;
-#pragma unroll
-      for (int q = 0; q < PF; ++q) {
-        int p = tid + q * NT;
-        if ((NL * N) % NT == 0 || p < NL * N) {
-          int zi = p % ZB, kx = (p / ZB) % N, cx = p / (ZB * N);
-          xb[(cx * ZB + zi) * P + kx] = pf[q];
-        }
-      }
       const Slot sl = st[k];
-      if (k + 1 < ns) fetch(k + 1);  // spectrum rows of the next slot
-      __syncthreads();
-      // inverse step 2 (per q1): IDFT_L2 over q2, conjugate twiddle; xb -> xo
-      constexpr int C2 = NL * L1;
-#pragma unroll
-      for (int it = tid; it < C2; it += NT) {
-        int line = it % NL, q1 = it / NL;
+      cpx<T>* xb = xo[k & 1];
+      if (s2) {
+        // inverse step 2 of item (line2, q12): IDFT_L2 over q2, conjugate twiddle
         cpx<T> w[L2];
 #pragma unroll
-        for (int q2 = 0; q2 < L2; ++q2) w[q2] = xb[line * P + q1 + L1 * q2];
+        for (int q2 = 0; q2 < L2; ++q2) w[q2] = nw[q2];
+        if (k + 1 < ns) fetch(k + 1);  // spectrum rows of the next slot
         Dft<L2, 1, T>::run(w);
 #pragma unroll
-        for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q1]);
+        for (int t = 1; t < L2; ++t) w[t] = cmulc(w[t], tw[t * q12]);
 #pragma unroll
-        for (int t = 0; t < L2; ++t) xo[line * P + t + L2 * q1] = w[t];
+        for (int t = 0; t < L2; ++t) xb[line2 * P + t + L2 * q12] = w[t];
       }
       __syncthreads();
       // inverse step 1 (per t) of both x classes, demodulated: V_a + i V_b at the
@@ -1765,7 +1759,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       {
         cpx<T> v[L1];
 #pragma unroll
-        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[zi_own * P + t_own + L2 * q1];
+        for (int q1 = 0; q1 < L1; ++q1) v[q1] = xb[zi_own * P + t_own + L2 * q1];
         Dft<L1, 1, T>::run(v);
 #pragma unroll
         for (int k1 = 0; k1 < LP; ++k1)
@@ -1774,7 +1768,7 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
                                    pick(hmask, v[k1].y, v[min(LP % L1 + k1, L1 - 1)].y)};
         if (NCLS == 2) {
 #pragma unroll
-          for (int q1 = 0; q1 < L1; ++q1) v[q1] = xo[(ZB + zi_own) * P + t_own + L2 * q1];
+          for (int q1 = 0; q1 < L1; ++q1) v[q1] = xb[(ZB + zi_own) * P + t_own + L2 * q1];
           Dft<L1, 1, T>::run(v);
 #pragma unroll
           for (int k1 = 0; k1 < LP; ++k1) {
