@@ -1734,6 +1734,16 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
         pI[k1] = kok(k1) ? po[t_own + L2 * kcl(k1)] : T(0);
       }
     }
+    // K psi of row a at the owned points, read here so that the read overlaps
+    // the row's slots (no other block of the launch touches these points, and
+    // this block writes them only at the row's end)
+    double kold[LP];
+    const bool rmw = want_k && !(want_k == 2 && tp.diag);
+    if (rmw) {
+      const double* ko = kpsi_s + (size_t)(tp.I0 + a) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < LP; ++k1) kold[k1] = kok(k1) ? ko[t_own + L2 * (k0 + k1)] : 0.0;
+    }
     const double fa = fI[a];
 #pragma unroll
     for (int bb = 0; bb < HB; ++bb) {
@@ -1827,14 +1837,14 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
 #pragma unroll
             for (int k1 = 0; k1 < LP; ++k1) accI[k1] += accJ[b][k1];
       }
-      if (want_k == 2 && tp.diag) {  // first write of this orbital row in the evaluation
+      if (!rmw) {  // first write of this orbital row in the evaluation
 #pragma unroll
         for (int k1 = 0; k1 < LP; ++k1)
           if (kok(k1)) ko[t_own + L2 * (k0 + k1)] = accI[k1];
       } else {
 #pragma unroll
         for (int k1 = 0; k1 < LP; ++k1)
-          if (kok(k1)) ko[t_own + L2 * (k0 + k1)] += accI[k1];
+          if (kok(k1)) ko[t_own + L2 * (k0 + k1)] = kold[k1] + accI[k1];
       }
     }
   }
