@@ -2005,6 +2005,16 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
         pI[k1] = po[t_own + L2 * k1];
       }
     }
+    // K psi of row a, read here so that the read overlaps the row's slots (no
+    // other block of the launch touches these points; this block writes them
+    // at the row's end); zero where the row's first write of the evaluation is
+    const bool first = want_k == 2 && tp.diag;
+    cpx<double> kold[L1];
+    if (want_k) {
+      const cpx<double>* ko = kpsi_s + (size_t)(tp.I0 + a) * M3 + row;
+#pragma unroll
+      for (int k1 = 0; k1 < L1; ++k1) kold[k1] = first ? cpx<double>{0.0, 0.0} : ko[t_own + L2 * k1];
+    }
     const double fa = fI[a];
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
@@ -2092,10 +2102,9 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
               accI[k1][1] += accJ[b][k1][1];
             }
       }
-      const bool first = want_k == 2 && tp.diag;  // first write of this orbital row
 #pragma unroll
       for (int k1 = 0; k1 < L1; ++k1) {
-        cpx<double> v = first ? cpx<double>{0.0, 0.0} : ko[t_own + L2 * k1];
+        cpx<double> v = kold[k1];
         v.x += accI[k1][0];
         v.y += accI[k1][1];
         ko[t_own + L2 * k1] = v;
