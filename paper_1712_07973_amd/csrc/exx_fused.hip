@@ -1708,6 +1708,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
       for (int q2 = 0; q2 < L2; ++q2) nw[q2] = load_stream(Xs + (size_t)L1 * q2 * ZB);
     }
   };
+  // the first slot's spectrum rows, in flight with the orbital loads below
+  if (ns > 0) fetch(0);
   // orbital values at the owned points: every J-side orbital of the tile once
   // into LDS (slot [b][k1 NT + tid], read back by the same thread only), the
   // I-side orbital once per row into registers
@@ -1719,7 +1721,6 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     for (int k1 = 0; k1 < LP; ++k1) pJs[b][k1 * NT + tid] = kok(k1) ? po[t_own + L2 * kcl(k1)] : T(0);
   }
   __syncthreads();
-  if (ns > 0) fetch(0);
 
   int k = 0;  // running slot index (uniform)
 #pragma unroll 1
@@ -1982,6 +1983,7 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
       if ((NL * N) % NT == 0 || p < NL * N) pf[q] = load_stream(Xs + p);
     }
   };
+  if (ns > 0) fetch(0);  // in flight with the orbital loads below
 #pragma unroll
   for (int b = 0; b < TM; ++b) {
     if (b >= tp.nJ) continue;
@@ -1990,7 +1992,6 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
     for (int k1 = 0; k1 < L1; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * k1];
   }
   __syncthreads();
-  if (ns > 0) fetch(0);
 
   int k = 0;  // running slot index (uniform)
 #pragma unroll 1
