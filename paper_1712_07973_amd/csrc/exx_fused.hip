@@ -181,10 +181,6 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
   const int ls1 = ls0 + SPB < nslots ? ls0 + SPB : nslots;
   const size_t M3 = (size_t)N * N * N;
 
-  for (int k = tid; k < N; k += NT) {
-    tw[k] = twg[k];
-    if (NCLS == 2) md[k] = mdg[k];
-  }
   // orbital values of slot ls at the block's points p = tid + q NT -> (zi, x)
   // (CPLX: va = psi_i, vb = psi_j as (re, im))
   T va[PV][2], vb[PV][2];
@@ -229,6 +225,12 @@ __global__ __launch_bounds__(NT) void k_pass_a(const T* __restrict__ psi, cpx<T>
     }
   };
   if (ls0 < ls1) fetch(ls0);
+  // the tables, loaded while the first slot's orbital values are in flight
+  // (first read after the loop's first barrier)
+  for (int k = tid; k < N; k += NT) {
+    tw[k] = twg[k];
+    if (NCLS == 2) md[k] = mdg[k];
+  }
 
 #pragma unroll 1
   for (int ls = ls0; ls < ls1; ++ls) {
