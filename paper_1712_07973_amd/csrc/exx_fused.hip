@@ -1670,6 +1670,35 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
   const int ns = tp.s1 - tp.s0;
 
+  // spectrum rows of a slot: the block's rows are one contiguous z-block chunk
+  // of the slot, value (cx, kx, zi) at (cx N + kx) ZB + zi.  Step-2 item (line,
+  // q1) = (tid mod NL, tid / NL), line = cx ZB + zi, takes kx = q1 + L1 q2: its
+  // thread loads them straight into registers, one slot ahead (a wavefront's
+  // loads are 256-byte runs of two kx at 16 zi)
+  const bool s2 = tid < C2;
+  const int line2 = tid % NL, q12 = tid / NL;
+  cpx<T> nw[L2];
+  auto fetch = [&](int k) {
+    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N +
+                       (size_t)((line2 / ZB) * N + q12) * ZB + line2 % ZB;
+    if (s2) {
+#pragma unroll
+      for (int q2 = 0; q2 < L2; ++q2) nw[q2] = load_stream(Xs + (size_t)L1 * q2 * ZB);
+    }
+  };
+  // The block's first global loads go out together, so that their latencies
+  // overlap: the first slot's spectrum rows, the orbital values at the owned
+  // points (every J-side orbital of the tile once, parked in LDS below; the
+  // I-side orbital once per row), then the tables, occupations and slots.
+  if (ns > 0) fetch(0);
+  T pjr[TM][LP];
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const T* po = psi + (size_t)(tp.J0 + b) * M3 + row;
+#pragma unroll
+    for (int k1 = 0; k1 < LP; ++k1)
+      pjr[b][k1] = (b < tp.nJ && kok(k1)) ? po[t_own + L2 * kcl(k1)] : T(0);
+  }
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
@@ -1694,34 +1723,12 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
     for (int k1 = 0; k1 < LP; ++k1) accJ[b][k1] = 0.0;
   double ew = 0.0;
 
-  // spectrum rows of a slot: the block's rows are one contiguous z-block chunk
-  // of the slot, value (cx, kx, zi) at (cx N + kx) ZB + zi.  Step-2 item (line,
-  // q1) = (tid mod NL, tid / NL), line = cx ZB + zi, takes kx = q1 + L1 q2: its
-  // thread loads them straight into registers, one slot ahead (a wavefront's
-  // loads are 256-byte runs of two kx at 16 zi)
-  const bool s2 = tid < C2;
-  const int line2 = tid % NL, q12 = tid / NL;
-  cpx<T> nw[L2];
-  auto fetch = [&](int k) {
-    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N +
-                       (size_t)((line2 / ZB) * N + q12) * ZB + line2 % ZB;
-    if (s2) {
+  // the J-side orbital values into LDS (slot [b][k1 NT + tid], read back by the
+  // same thread only)
 #pragma unroll
-      for (int q2 = 0; q2 < L2; ++q2) nw[q2] = load_stream(Xs + (size_t)L1 * q2 * ZB);
-    }
-  };
-  // the first slot's spectrum rows, in flight with the orbital loads below
-  if (ns > 0) fetch(0);
-  // orbital values at the owned points: every J-side orbital of the tile once
-  // into LDS (slot [b][k1 NT + tid], read back by the same thread only), the
-  // I-side orbital once per row into registers
+  for (int b = 0; b < TM; ++b)
 #pragma unroll
-  for (int b = 0; b < TM; ++b) {
-    if (b >= tp.nJ) continue;
-    const T* po = psi + (size_t)(tp.J0 + b) * M3 + row;
-#pragma unroll
-    for (int k1 = 0; k1 < LP; ++k1) pJs[b][k1 * NT + tid] = kok(k1) ? po[t_own + L2 * kcl(k1)] : T(0);
-  }
+    for (int k1 = 0; k1 < LP; ++k1) pJs[b][k1 * NT + tid] = pjr[b][k1];
   __syncthreads();
 
   int k = 0;  // running slot index (uniform)
