@@ -1962,6 +1962,27 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
   const size_t row = swap_yz ? ((size_t)y * N + z0 + zi_own) * N : ((size_t)(z0 + zi_own) * N + y) * N;
   const int ns = tp.s1 - tp.s0;
 
+  cpx<T> pf[PF];
+  auto fetch = [&](int k) {
+    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N;
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      int p = tid + q * NT;
+      if ((NL * N) % NT == 0 || p < NL * N) pf[q] = load_stream(Xs + p);
+    }
+  };
+  // the block's first global loads go out together (as in the real pass C):
+  // the first slot's spectrum rows, the tile's J-side orbital values, then the
+  // tables, occupations and slots
+  if (ns > 0) fetch(0);
+  cpx<T> pjr[TM][L1];
+#pragma unroll
+  for (int b = 0; b < TM; ++b) {
+    const cpx<T>* po = psi + (size_t)(tp.J0 + b) * M3 + row;
+#pragma unroll
+    for (int k1 = 0; k1 < L1; ++k1)
+      pjr[b][k1] = b < tp.nJ ? po[t_own + L2 * k1] : cpx<T>{T(0), T(0)};
+  }
   for (int k = tid; k < N; k += NT) {
     tw[k] = twg[k];
     if (NCLS == 2) md[k] = mdg[k];
@@ -1983,23 +2004,12 @@ __global__ __launch_bounds__(NT, (pass_c_cplx_min_waves<T, N>())) void k_pass_c_
     for (int k1 = 0; k1 < L1; ++k1) accJ[b][k1][0] = accJ[b][k1][1] = 0.0;
   double ew = 0.0;
 
-  cpx<T> pf[PF];
-  auto fetch = [&](int k) {
-    const cpx<T>* Xs = X + (size_t)(tp.s0 + k - slot_base) * NCLS * M3 + (size_t)blockIdx.x * NL * N;
+  // the J-side orbital values into LDS (slot [b][k1 NT + tid], read back by the
+  // same thread only)
 #pragma unroll
-    for (int q = 0; q < PF; ++q) {
-      int p = tid + q * NT;
-      if ((NL * N) % NT == 0 || p < NL * N) pf[q] = load_stream(Xs + p);
-    }
-  };
-  if (ns > 0) fetch(0);  // in flight with the orbital loads below
+  for (int b = 0; b < TM; ++b)
 #pragma unroll
-  for (int b = 0; b < TM; ++b) {
-    if (b >= tp.nJ) continue;
-    const cpx<T>* po = psi + (size_t)(tp.J0 + b) * M3 + row;
-#pragma unroll
-    for (int k1 = 0; k1 < L1; ++k1) pJs[b][k1 * NT + tid] = po[t_own + L2 * k1];
-  }
+    for (int k1 = 0; k1 < L1; ++k1) pJs[b][k1 * NT + tid] = pjr[b][k1];
   __syncthreads();
 
   int k = 0;  // running slot index (uniform)
