@@ -1556,8 +1556,11 @@ __global__ __launch_bounds__(NT) void k_pass_b3(cpx<T>* __restrict__ X, const cp
 // is added into K psi when its row is done.  The tile pairs of one launch
 // share no orbital (round-robin schedule), so every update of K psi is a plain
 // read-modify-write: no atomics, and results do not depend on scheduling.
-// The next slot's spectrum rows and orbital values are prefetched into
-// registers while the current slot is reduced.
+// A block issues its first global loads together (the first slot's spectrum
+// rows, the J-side orbital values, tables, occupations, slots); the next slot's
+// spectrum rows go into the step-2 threads' registers while the current slot
+// is reduced, the K psi of row a is read when the row starts, and a slot takes
+// one workgroup barrier (two row buffers in LDS).
 // Energies: with pair_out, one partial per (slot half, block) for the
 // pair-energy matrix; otherwise one weighted partial per block
 // (sum over the block's pairs of w f_i f_j e_ij, w = 2 off the diagonal).
@@ -1673,8 +1676,8 @@ __global__ __launch_bounds__(NT, (pass_c_min_waves<T, N>())) void k_pass_c(const
   // spectrum rows of a slot: the block's rows are one contiguous z-block chunk
   // of the slot, value (cx, kx, zi) at (cx N + kx) ZB + zi.  Step-2 item (line,
   // q1) = (tid mod NL, tid / NL), line = cx ZB + zi, takes kx = q1 + L1 q2: its
-  // thread loads them straight into registers, one slot ahead (a wavefront's
-  // loads are 256-byte runs of two kx at 16 zi)
+  // thread loads them straight into registers, one slot ahead (each load of a
+  // wavefront reads whole 128-byte runs of 16 zi at consecutive kx)
   const bool s2 = tid < C2;
   const int line2 = tid % NL, q12 = tid / NL;
   cpx<T> nw[L2];
